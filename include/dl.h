@@ -1,0 +1,162 @@
+/*
+ * dl.h - C ABI of the MI355X (gfx950) dictionary-learning library.
+ *
+ * The library runs one or more iterations of dictionary learning with Jacobi
+ * atom updates (Irofti & Dumitrescu, "Overcomplete Dictionary Learning with
+ * Jacobi Atom Updates"):
+ *   step 1 (Alg. 1): sparse coding of every signal with OMP at fixed sparsity s,
+ *            computed as Batch-OMP from G = D^T D and D^T Y;
+ *   step 2 (Alg. 1, Alg. 2): atoms updated in groups of `group_size`; every atom
+ *            of a group is refreshed from the same error E = Y - D X with the
+ *            AK-SVD rule (eq. 5), normalised, and the group is committed before
+ *            the next one starts (eq. 2);
+ *   error  : ||Y - D X||_F / sqrt(p m) after the update, with the refreshed X.
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller, aligned to
+ *     16 bytes (the workspace to 256 bytes).  The library never allocates or
+ *     frees device memory and never synchronises the stream, except where an
+ *     entry point says so.
+ *   - Layouts are row-major:
+ *       D  [n][p] float   atom j is D + j*p (unit-norm rows)
+ *       Y  [m][p] float   signal i is Y + i*p
+ *       X  ELL: X_idx [m][s] int32 atom index, -1 in unused slots;
+ *               X_val [m][s] float coefficient, 0 in unused slots.
+ *               Slot t of signal i holds the t-th atom OMP selected.
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *   - Arguments are validated on the host before anything is launched; a
+ *     failure returns DL_EINVAL or DL_EWORKSPACE and enqueues nothing.
+ *   - A launch failure returns DL_EHIP.  Non-finite values met on the device
+ *     are counted in the workspace statistics; dl_read_stats reports them as
+ *     DL_ENUMERIC.
+ *   - Calls that share a workspace must not overlap in time (use one stream).
+ *   - No C++ exception crosses this boundary.
+ *
+ * Limits: 4 <= p <= 256 with p % 4 == 0; 1 <= n <= 1024; 1 <= s <= min(p, n, 16);
+ * m >= 1 with m * s < 2^31; group_size >= 1 (values above n mean n).
+ */
+#ifndef DL_MI355_H
+#define DL_MI355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *dl_stream_t; /* the same handle type as hipStream_t */
+
+typedef enum {
+    DL_OK = 0,
+    DL_EINVAL = -1,       /* bad size, pointer, alignment or option */
+    DL_EWORKSPACE = -2,   /* workspace smaller than dl_workspace_size() */
+    DL_EHIP = -3,         /* a HIP launch or copy failed */
+    DL_ENUMERIC = -4,     /* non-finite values were met on the device */
+    DL_EUNSUPPORTED = -5  /* option valid in principle but not built */
+} dl_status;
+
+typedef enum { DL_PREC_FP32 = 0, DL_PREC_BF16 = 1 } dl_precision;
+
+/* Atom rule.  AK-SVD (eq. 5): d = F x^T / ||F x^T||, then x = F^T d (X is
+   refreshed).  SGK (eq. 6): d = F x^T / (x x^T), normalised; X unchanged. */
+typedef enum { DL_RULE_AKSVD = 0, DL_RULE_SGK = 1 } dl_rule;
+
+typedef struct dl_params {
+    int p, n, m, s;               /* signal size, atoms, signals, sparsity */
+    int group_size;               /* atoms updated in parallel (eq. 2); >= n: all at once */
+    int precision;                /* dl_precision of D^T Y, D^T D and the residual products */
+    int rule;                     /* dl_rule */
+    float pivot_fp64_threshold;   /* FP32 Cholesky pivots below this are recomputed in FP64 (1e-6) */
+    float tol_corr;               /* OMP stops when max |d_j^T r| <= tol_corr * ||y|| (1e-5) */
+    float tol_pivot;              /* OMP stops when the FP64 pivot <= tol_pivot * G_jj (1e-10) */
+} dl_params;
+
+/* Counters kept in the workspace (device); read them with dl_read_stats. */
+typedef struct dl_stats {
+    long long fp64_pivot_recomputes; /* OMP steps whose pivot was recomputed in FP64 */
+    long long early_stops;           /* signals coded with fewer than s atoms */
+    long long unused_atoms;          /* atom updates skipped: the atom had no users */
+    long long zero_updates;          /* atom updates skipped: F x^T was zero */
+    long long nonfinite;             /* non-finite values met (inputs or results) */
+    long long fallbacks;             /* learned-proposal signals handed back to OMP */
+} dl_stats;
+
+/* ABI version of this header (increments on any signature change). */
+int dl_abi_version(void);
+
+/* Human-readable name of a dl_status value. */
+const char *dl_status_string(int status);
+
+/* Fill *prm with the defaults for a problem of the given sizes
+   (group_size = n, FP32, AK-SVD, thresholds as documented above). */
+dl_status dl_params_default(dl_params *prm, int p, int n, int m, int s);
+
+/* Bytes of workspace the calls below need for these parameters (host only,
+   pure).  Returns 0 if the parameters are invalid. */
+size_t dl_workspace_size(const dl_params *prm);
+
+/* Zero the workspace's counters and control words.  Call once after
+   allocating a workspace (dl_iterate does it itself). */
+dl_status dl_workspace_init(const dl_params *prm, void *ws, size_t ws_bytes, dl_stream_t stream);
+
+/* G = D D^T as [n][n] (the Gram matrix of the atoms that Batch-OMP uses for
+   its incremental Cholesky; the paper's coder is OMP, Sec. 4).  FP32 MFMA
+   with FP32 accumulation (BF16 inputs when prm->precision is DL_PREC_BF16). */
+dl_status dl_gram(const dl_params *prm, const float *D, float *G, dl_stream_t stream);
+
+/* A0 = Y D^T as [m][n]: the correlations D^T y of every signal with every
+   atom, the first term of Batch-OMP's correlation update.  Same precision
+   rules as dl_gram. */
+dl_status dl_corr(const dl_params *prm, const float *D, const float *Y, float *A0,
+                  dl_stream_t stream);
+
+/* Step 1 of the DL iteration (Alg. 1): OMP with fixed sparsity s of every
+   signal against D, written to X_idx/X_val.  Ties between correlations go to
+   the lowest atom index.  A signal stops early when its residual is
+   numerically orthogonal to every atom (tol_corr) or the next atom's pivot
+   vanishes (tol_pivot); its remaining slots are (-1, 0).  Also leaves the
+   coding residual E = Y - D X in the workspace. */
+dl_status dl_omp(const dl_params *prm, const float *D, const float *Y, int32_t *X_idx,
+                 float *X_val, void *ws, size_t ws_bytes, dl_stream_t stream);
+
+/* The users of every atom (the set I_j of Sec. 3: signals whose representation
+   uses d_j), as a CSR transpose of X: row_ptr [n+1] and users [m*s]; entry
+   users[row_ptr[j] + r] is the ELL position i*s + t of the r-th use of atom j,
+   in increasing signal order.  Slots with index -1 are not listed.
+   Deterministic; the result is exact. */
+dl_status dl_csr(const dl_params *prm, const int32_t *X_idx, int32_t *row_ptr, int32_t *users,
+                 void *ws, size_t ws_bytes, dl_stream_t stream);
+
+/* Step 2 of the DL iteration: the Jacobi atom update of Alg. 2 with the rule
+   prm->rule, groups of prm->group_size atoms in index order.  D is replaced
+   by the new dictionary, X_val by the refreshed representations (AK-SVD; SGK
+   leaves them).  X_idx is not changed.  An atom with no users, or whose
+   F x^T is zero, keeps its value. */
+dl_status dl_jau_update(const dl_params *prm, const float *Y, float *D, const int32_t *X_idx,
+                        float *X_val, void *ws, size_t ws_bytes, dl_stream_t stream);
+
+/* rmse_out[0] = ||Y - D X||_F / sqrt(p m), accumulated in FP64 (the error the
+   paper plots, Sec. 4.2).  rmse_out is a device pointer to one double. */
+dl_status dl_rmse(const dl_params *prm, const float *Y, const float *D, const int32_t *X_idx,
+                  const float *X_val, double *rmse_out, void *ws, size_t ws_bytes,
+                  dl_stream_t stream);
+
+/* `iters` DL iterations (Alg. 1): D holds D0 on entry (it is normalised
+   first) and the final dictionary on exit; X_idx/X_val hold the last
+   iteration's representations after its update; rmse[k] (device, `iters`
+   doubles) is the error after iteration k.  Zeroes the workspace counters
+   first. */
+dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, int32_t *X_idx,
+                     float *X_val, double *rmse, void *ws, size_t ws_bytes, dl_stream_t stream);
+
+/* Synchronise `stream` and copy the workspace counters to *out (host).
+   Returns DL_ENUMERIC if any non-finite value was counted, else DL_OK. */
+dl_status dl_read_stats(const dl_params *prm, const void *ws, size_t ws_bytes, dl_stats *out,
+                        dl_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DL_MI355_H */

@@ -1,0 +1,432 @@
+// C ABI of the library (include/dl.h): argument validation, workspace
+// layout and the launch order of one DL iteration (Alg. 1):
+//   Gram G = D D^T, correlations A0 = Y D^T, OMP (+ residual E),
+//   users of every atom (CSR), group atom update, error.
+#include <string.h>
+
+#include "dl_internal.h"
+
+namespace dlk {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout_for(const dl_params &prm)
+{
+    const size_t p = prm.p, n = prm.n, m = prm.m, s = prm.s;
+    const size_t nb = (size_t)csr_blocks(prm.m);
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    L.control = take(sizeof(Control));
+    L.G = take(sizeof(float) * n * n);
+    L.A0 = take(sizeof(float) * m * n);
+    L.E = take(sizeof(float) * m * p);
+    L.Dn = take(sizeof(float) * n * p);
+    L.val_ws = take(sizeof(float) * m * s);
+    L.valn = take(sizeof(float) * m * s);
+    L.blkcnt = take(sizeof(int32_t) * nb * n);
+    L.lrank = take(sizeof(int32_t) * m * s);
+    L.row_ptr = take(sizeof(int32_t) * (n + 1));
+    L.chunk_ptr = take(sizeof(int32_t) * (n + 1));
+    L.users = take(sizeof(int32_t) * m * s);
+    L.atom_state = take(sizeof(int32_t) * n);
+    L.partial = take(sizeof(float) * (size_t)max_chunks(prm) * p);
+    L.rmse_part = take(sizeof(double) * kRmseBlocks);
+    if (prm.precision == DL_PREC_BF16) {
+        L.Dbf = take(sizeof(uint16_t) * n * p);
+        L.Ybf = take(sizeof(uint16_t) * m * p);
+    } else {
+        L.Dbf = L.Ybf = 0;
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace dlk
+
+using namespace dlk;
+
+namespace {
+
+bool valid_params(const dl_params *prm)
+{
+    if (!prm)
+        return false;
+    const dl_params &q = *prm;
+    if (q.p < 4 || q.p > 256 || q.p % 4 != 0)
+        return false;
+    if (q.n < 1 || q.n > 1024 || q.m < 1)
+        return false;
+    if (q.s < 1 || q.s > 16 || q.s > q.p || q.s > q.n)
+        return false;
+    if ((long long)q.m * q.s >= (1ll << 31) || (long long)q.m * q.n >= (1ll << 40))
+        return false;
+    if (q.group_size < 1)
+        return false;
+    if (q.precision != DL_PREC_FP32 && q.precision != DL_PREC_BF16)
+        return false;
+    if (q.precision == DL_PREC_BF16 && q.p % 8 != 0)
+        return false;
+    if (q.rule != DL_RULE_AKSVD && q.rule != DL_RULE_SGK)
+        return false;
+    if (!(q.pivot_fp64_threshold >= 0.f) || !(q.tol_corr >= 0.f) || !(q.tol_pivot >= 0.f))
+        return false;
+    return true;
+}
+
+bool aligned(const void *ptr, size_t a) { return ptr && ((uintptr_t)ptr % a) == 0; }
+
+struct Ws {
+    char *base;
+    Layout L;
+    template <class T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
+    Control *ctl() const { return at<Control>(L.control); }
+};
+
+dl_status check_ws(const dl_params *prm, const void *ws, size_t ws_bytes, Ws *out)
+{
+    if (!aligned(ws, 256))
+        return DL_EINVAL;
+    const Layout L = layout_for(*prm);
+    if (ws_bytes < L.total)
+        return DL_EWORKSPACE;
+    out->base = (char *)ws;
+    out->L = L;
+    return DL_OK;
+}
+
+#define DL_TRY(expr)                               \
+    do {                                           \
+        if ((expr) != hipSuccess)                  \
+            return DL_EHIP;                        \
+    } while (0)
+
+// G and A0 for the coding stage, in the precision the parameters ask for.
+dl_status products(const dl_params &prm, const float *D, const float *Y, float *G, float *A0,
+                   const Ws *ws, hipStream_t st)
+{
+    if (prm.precision == DL_PREC_BF16) {
+        uint16_t *Dbf = ws->at<uint16_t>(ws->L.Dbf);
+        uint16_t *Ybf = ws->at<uint16_t>(ws->L.Ybf);
+        DL_TRY(launch_cast_bf16(D, Dbf, (size_t)prm.n * prm.p, st));
+        DL_TRY(launch_cast_bf16(Y, Ybf, (size_t)prm.m * prm.p, st));
+        if (G)
+            DL_TRY(launch_gemm_nt_bf16(Dbf, Dbf, G, prm.n, prm.n, prm.p, st));
+        if (A0)
+            DL_TRY(launch_gemm_nt_bf16(Ybf, Dbf, A0, prm.m, prm.n, prm.p, st));
+    } else {
+        if (G)
+            DL_TRY(launch_gemm_nt_f32(D, D, G, prm.n, prm.n, prm.p, st));
+        if (A0)
+            DL_TRY(launch_gemm_nt_f32(Y, D, A0, prm.m, prm.n, prm.p, st));
+    }
+    return DL_OK;
+}
+
+dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t *idx, float *val,
+                  const Ws &ws, hipStream_t st)
+{
+    float *G = ws.at<float>(ws.L.G);
+    float *A0 = ws.at<float>(ws.L.A0);
+    dl_status rc = products(prm, D, Y, G, A0, &ws, st);
+    if (rc != DL_OK)
+        return rc;
+    OmpArgs a;
+    a.A0 = A0;
+    a.G = G;
+    a.Y = Y;
+    a.D = D;
+    a.idx = idx;
+    a.val = val;
+    a.E = ws.at<float>(ws.L.E);
+    a.ctl = ws.ctl();
+    a.p = prm.p;
+    a.n = prm.n;
+    a.m = prm.m;
+    a.s = prm.s;
+    a.pivot_fp64 = prm.pivot_fp64_threshold;
+    a.tol_corr = prm.tol_corr;
+    a.tol_pivot = prm.tol_pivot;
+    DL_TRY(launch_omp(a, st));
+    return DL_OK;
+}
+
+dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, int32_t *users,
+                  float *val_pad, const Ws &ws, hipStream_t st)
+{
+    CsrArgs c;
+    c.idx = idx;
+    c.blkcnt = ws.at<int32_t>(ws.L.blkcnt);
+    c.lrank = ws.at<int32_t>(ws.L.lrank);
+    c.row_ptr = row_ptr;
+    c.chunk_ptr = ws.at<int32_t>(ws.L.chunk_ptr);
+    c.users = users;
+    c.val_pad = val_pad;
+    c.n = prm.n;
+    c.m = prm.m;
+    c.s = prm.s;
+    DL_TRY(launch_csr(c, st));
+    return DL_OK;
+}
+
+// One atom-update sweep reading (D, val) and writing (Dn, valn); E must hold
+// Y - D X on entry.
+dl_status run_update(const dl_params &prm, const float *Y, const float *D, float *Dn,
+                     const int32_t *idx, const float *val, float *valn, const Ws &ws,
+                     hipStream_t st)
+{
+    int32_t *row_ptr = ws.at<int32_t>(ws.L.row_ptr);
+    int32_t *users = ws.at<int32_t>(ws.L.users);
+    dl_status rc = run_csr(prm, idx, row_ptr, users, valn, ws, st);
+    if (rc != DL_OK)
+        return rc;
+    UpdateArgs u;
+    u.Y = Y;
+    u.D = D;
+    u.Dn = Dn;
+    u.idx = idx;
+    u.val = val;
+    u.valn = valn;
+    u.E = ws.at<float>(ws.L.E);
+    u.row_ptr = row_ptr;
+    u.chunk_ptr = ws.at<int32_t>(ws.L.chunk_ptr);
+    u.users = users;
+    u.atom_state = ws.at<int32_t>(ws.L.atom_state);
+    u.partial = ws.at<float>(ws.L.partial);
+    u.ctl = ws.ctl();
+    u.p = prm.p;
+    u.n = prm.n;
+    u.m = prm.m;
+    u.s = prm.s;
+    u.group_size = prm.group_size;
+    u.rule = prm.rule;
+    u.max_chunks = max_chunks(prm);
+    DL_TRY(launch_update(u, st));
+    return DL_OK;
+}
+
+dl_status run_rmse(const dl_params &prm, const float *Y, const float *D, const int32_t *idx,
+                   const float *val, double *out, const Ws &ws, hipStream_t st)
+{
+    RmseArgs r;
+    r.Y = Y;
+    r.D = D;
+    r.idx = idx;
+    r.val = val;
+    r.partial = ws.at<double>(ws.L.rmse_part);
+    r.out = out;
+    r.ctl = ws.ctl();
+    r.p = prm.p;
+    r.n = prm.n;
+    r.m = prm.m;
+    r.s = prm.s;
+    DL_TRY(launch_rmse(r, st));
+    return DL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dl_abi_version(void) { return 1; }
+
+const char *dl_status_string(int status)
+{
+    switch (status) {
+    case DL_OK: return "DL_OK";
+    case DL_EINVAL: return "DL_EINVAL: invalid argument";
+    case DL_EWORKSPACE: return "DL_EWORKSPACE: workspace too small";
+    case DL_EHIP: return "DL_EHIP: HIP launch or copy failed";
+    case DL_ENUMERIC: return "DL_ENUMERIC: non-finite values met on the device";
+    case DL_EUNSUPPORTED: return "DL_EUNSUPPORTED: option not built";
+    default: return "unknown dl_status";
+    }
+}
+
+dl_status dl_params_default(dl_params *prm, int p, int n, int m, int s)
+{
+    if (!prm)
+        return DL_EINVAL;
+    memset(prm, 0, sizeof(*prm));
+    prm->p = p;
+    prm->n = n;
+    prm->m = m;
+    prm->s = s;
+    prm->group_size = n;
+    prm->precision = DL_PREC_FP32;
+    prm->rule = DL_RULE_AKSVD;
+    prm->pivot_fp64_threshold = 1e-6f;
+    prm->tol_corr = 1e-5f;
+    prm->tol_pivot = 1e-10f;
+    return valid_params(prm) ? DL_OK : DL_EINVAL;
+}
+
+size_t dl_workspace_size(const dl_params *prm)
+{
+    if (!valid_params(prm))
+        return 0;
+    return layout_for(*prm).total;
+}
+
+dl_status dl_workspace_init(const dl_params *prm, void *ws, size_t ws_bytes, dl_stream_t stream)
+{
+    if (!valid_params(prm))
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    DL_TRY(launch_zero(w.ctl(), sizeof(Control), (hipStream_t)stream));
+    return DL_OK;
+}
+
+dl_status dl_gram(const dl_params *prm, const float *D, float *G, dl_stream_t stream)
+{
+    if (!valid_params(prm) || !aligned(D, 16) || !aligned(G, 16))
+        return DL_EINVAL;
+    if (prm->precision != DL_PREC_FP32)
+        return DL_EUNSUPPORTED;  // the BF16 product needs the workspace: use dl_omp
+    DL_TRY(launch_gemm_nt_f32(D, D, G, prm->n, prm->n, prm->p, (hipStream_t)stream));
+    return DL_OK;
+}
+
+dl_status dl_corr(const dl_params *prm, const float *D, const float *Y, float *A0,
+                  dl_stream_t stream)
+{
+    if (!valid_params(prm) || !aligned(D, 16) || !aligned(Y, 16) || !aligned(A0, 16))
+        return DL_EINVAL;
+    if (prm->precision != DL_PREC_FP32)
+        return DL_EUNSUPPORTED;
+    DL_TRY(launch_gemm_nt_f32(Y, D, A0, prm->m, prm->n, prm->p, (hipStream_t)stream));
+    return DL_OK;
+}
+
+dl_status dl_omp(const dl_params *prm, const float *D, const float *Y, int32_t *X_idx,
+                 float *X_val, void *ws, size_t ws_bytes, dl_stream_t stream)
+{
+    if (!valid_params(prm) || !aligned(D, 16) || !aligned(Y, 16) || !aligned(X_idx, 4) ||
+        !aligned(X_val, 4))
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    return run_omp(*prm, D, Y, X_idx, X_val, w, (hipStream_t)stream);
+}
+
+dl_status dl_csr(const dl_params *prm, const int32_t *X_idx, int32_t *row_ptr, int32_t *users,
+                 void *ws, size_t ws_bytes, dl_stream_t stream)
+{
+    if (!valid_params(prm) || !aligned(X_idx, 4) || !aligned(row_ptr, 4) || !aligned(users, 4))
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    return run_csr(*prm, X_idx, row_ptr, users, nullptr, w, (hipStream_t)stream);
+}
+
+dl_status dl_jau_update(const dl_params *prm, const float *Y, float *D, const int32_t *X_idx,
+                        float *X_val, void *ws, size_t ws_bytes, dl_stream_t stream)
+{
+    if (!valid_params(prm) || !aligned(Y, 16) || !aligned(D, 16) || !aligned(X_idx, 4) ||
+        !aligned(X_val, 4))
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const dl_params &q = *prm;
+    float *E = w.at<float>(w.L.E);
+    float *Dn = w.at<float>(w.L.Dn);
+    float *valn = w.at<float>(w.L.valn);
+    // E = Y - D X of the given representations (the first group's error)
+    DL_TRY(launch_residual(Y, D, X_idx, X_val, E, q.p, q.n, q.m, q.s, st));
+    rc = run_update(q, Y, D, Dn, X_idx, X_val, valn, w, st);
+    if (rc != DL_OK)
+        return rc;
+    DL_TRY(launch_copy(Dn, D, sizeof(float) * (size_t)q.n * q.p, st));
+    DL_TRY(launch_copy(valn, X_val, sizeof(float) * (size_t)q.m * q.s, st));
+    return DL_OK;
+}
+
+dl_status dl_rmse(const dl_params *prm, const float *Y, const float *D, const int32_t *X_idx,
+                  const float *X_val, double *rmse_out, void *ws, size_t ws_bytes,
+                  dl_stream_t stream)
+{
+    if (!valid_params(prm) || !aligned(Y, 16) || !aligned(D, 16) || !aligned(X_idx, 4) ||
+        !aligned(X_val, 4) || !aligned(rmse_out, 8))
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    return run_rmse(*prm, Y, D, X_idx, X_val, rmse_out, w, (hipStream_t)stream);
+}
+
+dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, int32_t *X_idx,
+                     float *X_val, double *rmse, void *ws, size_t ws_bytes, dl_stream_t stream)
+{
+    if (!valid_params(prm) || iters < 0 || !aligned(Y, 16) || !aligned(D, 16) ||
+        !aligned(X_idx, 4) || !aligned(X_val, 4) || (iters > 0 && !aligned(rmse, 8)))
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const dl_params &q = *prm;
+    DL_TRY(launch_zero(w.ctl(), sizeof(Control), st));
+    DL_TRY(launch_normalize_rows(D, q.n, q.p, w.ctl(), st));
+    float *Dws = w.at<float>(w.L.Dn);
+    float *val_ws = w.at<float>(w.L.val_ws);
+    // the dictionary alternates between the caller's buffer and the workspace
+    float *Dcur = D, *Dnext = Dws;
+    for (int k = 0; k < iters; ++k) {
+        rc = run_omp(q, Dcur, Y, X_idx, val_ws, w, st);
+        if (rc != DL_OK)
+            return rc;
+        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st);
+        if (rc != DL_OK)
+            return rc;
+        rc = run_rmse(q, Y, Dnext, X_idx, X_val, rmse + k, w, st);
+        if (rc != DL_OK)
+            return rc;
+        float *t = Dcur;
+        Dcur = Dnext;
+        Dnext = t;
+    }
+    if (Dcur != D)
+        DL_TRY(launch_copy(Dcur, D, sizeof(float) * (size_t)q.n * q.p, st));
+    return DL_OK;
+}
+
+dl_status dl_read_stats(const dl_params *prm, const void *ws, size_t ws_bytes, dl_stats *out,
+                        dl_stream_t stream)
+{
+    if (!valid_params(prm) || !out)
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    Control c;
+    DL_TRY(hipMemcpyAsync(&c, w.ctl(), sizeof(Control), hipMemcpyDeviceToHost,
+                          (hipStream_t)stream));
+    DL_TRY(hipStreamSynchronize((hipStream_t)stream));
+    out->fp64_pivot_recomputes = (long long)c.fp64_pivot_recomputes;
+    out->early_stops = (long long)c.early_stops;
+    out->unused_atoms = (long long)c.unused_atoms;
+    out->zero_updates = (long long)c.zero_updates;
+    out->nonfinite = (long long)c.nonfinite;
+    out->fallbacks = (long long)c.fallbacks;
+    return c.nonfinite ? DL_ENUMERIC : DL_OK;
+}
+
+}  // extern "C"

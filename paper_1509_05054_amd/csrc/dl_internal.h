@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP translation units of the library.
+// Nothing here is part of the C ABI (include/dl.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/dl.h"
+
+namespace dlk {
+
+// Users of one atom are processed in chunks of this many (atom update).
+constexpr int kChunk = 256;
+// Signals per block of the CSR transpose (one workgroup each).
+constexpr int kCsrBlock = 256;
+// Workgroups of the FP64 error reduction.
+constexpr int kRmseBlocks = 512;
+
+// Device-side counters and control words at the start of the workspace.
+struct Control {
+    unsigned long long fp64_pivot_recomputes;
+    unsigned long long early_stops;
+    unsigned long long unused_atoms;
+    unsigned long long zero_updates;
+    unsigned long long nonfinite;
+    unsigned long long fallbacks;
+    unsigned int rmse_done;  // arrival counter of the error reduction (self-resetting)
+    unsigned int pad[15];
+};
+
+// Byte offsets of the workspace regions (each 256-byte aligned).
+struct Layout {
+    size_t control;
+    size_t G;          // [n][n] float
+    size_t A0;         // [m][n] float, D^T y per signal
+    size_t E;          // [m][p] float, residual
+    size_t Dn;         // [n][p] float, next dictionary
+    size_t val_ws;     // [m][s] float, OMP coefficients before the update
+    size_t valn;       // [m][s] float, refreshed coefficients (dl_jau_update)
+    size_t blkcnt;     // [nb][n] int, per-block atom counts, then offsets
+    size_t lrank;      // [m*s] int, rank of an entry among its block's uses of the atom
+    size_t row_ptr;    // [n+1] int
+    size_t chunk_ptr;  // [n+1] int
+    size_t users;      // [m*s] int
+    size_t atom_state; // [n] int: 0 updated, 1 no users, 2 zero F x^T
+    size_t partial;    // [max_chunks][p] float
+    size_t rmse_part;  // [kRmseBlocks] double
+    size_t Dbf;        // [n][p] bf16 (precision variant)
+    size_t Ybf;        // [m][p] bf16 (precision variant)
+    size_t total;
+};
+
+Layout layout_for(const dl_params &prm);
+int csr_blocks(int m);
+int max_chunks(const dl_params &prm);
+
+// ---- launchers (return hipSuccess or the launch error) -------------------
+// C[M][N] = A[M][K] * B[N][K]^T, FP32 inputs, FP32 accumulation on MFMA.
+hipError_t launch_gemm_nt_f32(const float *A, const float *B, float *C, int M, int N, int K,
+                              hipStream_t st);
+// Same with BF16 inputs (uint16 bit patterns).
+hipError_t launch_gemm_nt_bf16(const uint16_t *A, const uint16_t *B, float *C, int M, int N,
+                               int K, hipStream_t st);
+// Round FP32 to BF16 (nearest even).
+hipError_t launch_cast_bf16(const float *x, uint16_t *y, size_t count, hipStream_t st);
+
+struct OmpArgs {
+    const float *A0;   // [m][n]
+    const float *G;    // [n][n]
+    const float *Y;    // [m][p]
+    const float *D;    // [n][p]
+    int32_t *idx;      // [m][s]
+    float *val;        // [m][s]
+    float *E;          // [m][p] residual, may be null
+    Control *ctl;
+    int p, n, m, s;
+    float pivot_fp64, tol_corr, tol_pivot;
+};
+hipError_t launch_omp(const OmpArgs &a, hipStream_t st);
+
+struct CsrArgs {
+    const int32_t *idx;  // [m][s]
+    int32_t *blkcnt;     // [nb][n]
+    int32_t *lrank;      // [m*s]
+    int32_t *row_ptr;    // [n+1]
+    int32_t *chunk_ptr;  // [n+1]
+    int32_t *users;      // [m*s]
+    float *val_pad;      // optional: zero written at padding slots
+    int n, m, s;
+};
+hipError_t launch_csr(const CsrArgs &a, hipStream_t st);
+
+struct UpdateArgs {
+    const float *Y;       // [m][p]
+    const float *D;       // [n][p] dictionary at the start of the sweep
+    float *Dn;            // [n][p] next dictionary
+    const int32_t *idx;   // [m][s]
+    const float *val;     // [m][s] coefficients at the start of the sweep
+    float *valn;          // [m][s] refreshed coefficients
+    float *E;             // [m][p] residual with the current D, X (kept up to date across groups)
+    const int32_t *row_ptr, *chunk_ptr, *users;
+    int32_t *atom_state;
+    float *partial;
+    Control *ctl;
+    int p, n, m, s, group_size, rule, max_chunks;
+};
+hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
+
+struct RmseArgs {
+    const float *Y, *D;
+    const int32_t *idx;
+    const float *val;
+    double *partial;  // [kRmseBlocks]
+    double *out;      // one double
+    Control *ctl;
+    int p, n, m, s;
+};
+hipError_t launch_rmse(const RmseArgs &a, hipStream_t st);
+
+// E = Y - D X (one signal per lane group).
+hipError_t launch_residual(const float *Y, const float *D, const int32_t *idx, const float *val,
+                           float *E, int p, int n, int m, int s, hipStream_t st);
+hipError_t launch_normalize_rows(float *D, int n, int p, Control *ctl, hipStream_t st);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+hipError_t launch_zero(void *dst, size_t bytes, hipStream_t st);
+
+}  // namespace dlk

@@ -1,0 +1,471 @@
+// Atom-update stage (step 2 of the DL iteration): the group loop of Alg. 2
+// with the AK-SVD rule of eq. (5) (or SGK, eq. 6), and the error.
+//
+// For group l (atoms [a0, a1)), every atom j of the group reads the same
+// group-start dictionary, representations and error E (the rule of eq. 2):
+//   pass 1 : g_j = F x_j^T = sum_{i in I_j} (e_i + d_j x_ji) x_ji   (eq. 3)
+//            over chunks of kChunk users, one workgroup per chunk, partial
+//            sums written per chunk (no float atomics);
+//   reduce : g_j summed over its chunks in chunk order, d_j' = g_j / ||g_j||
+//            (eq. 5, first line; SGK's least-squares atom has the same
+//            direction), written to the next dictionary Dn;
+//   pass 2 : AK-SVD refresh x_ji' = (e_i + d_j x_ji)^T d_j' (eq. 5, second
+//            line), written to valn;
+//   E      : for group sizes below n, E is brought up to date for the next
+//            group: e_i += d_j x_ji - d_j' x_ji' over the group's atoms that
+//            signal i uses (the incremental error update the paper mentions
+//            in Sec. 3), one signal at a time, so no two writers meet.
+//
+// Lane mapping of the per-user work: a user's p-vector is split over LPU
+// lanes (LPU = power of two >= p/4), each lane owning 4 consecutive
+// coordinates (float4), so one wave handles 64/LPU users at once.
+#include "dl_internal.h"
+
+namespace dlk {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int lanes_per_user(int p)
+{
+    int l = 1;
+    while (4 * l < p)
+        l <<= 1;
+    return l;
+}
+
+__device__ inline f32x4 load4(const float *base, int q, int p)
+{
+    if (q < p)
+        return *reinterpret_cast<const f32x4 *>(base + q);
+    return f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Atom of global chunk gc among atoms [a0, a1): chunk_ptr[j] <= gc < chunk_ptr[j+1].
+__device__ inline int chunk_atom(const int32_t *chunk_ptr, int a0, int a1, int gc)
+{
+    int lo = a0, hi = a1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chunk_ptr[mid] <= gc)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- pass 1: partial F x^T per chunk ------------------------------------
+__global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1)
+{
+    __shared__ f32x4 red[4][64];
+    const int p = a.p, s = a.s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lpu = lanes_per_user(p);
+    const int upw = 64 / lpu;       // users per wave step
+    const int sub = lane / lpu;     // user slot of this lane
+    const int q = 4 * (lane % lpu); // first coordinate of this lane
+    const int cbase = a.chunk_ptr[a0];
+    const int nch = a.chunk_ptr[a1] - cbase;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int gc = cbase + c;
+        const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
+        const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
+        const int u1 = min(u0 + kChunk, a.row_ptr[j + 1]);
+        const f32x4 d = load4(a.D + (size_t)j * p, q, p);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int u = u0 + wave * upw + sub; u < u1; u += 4 * upw) {
+            const int pos = a.users[u];
+            const int i = pos / s;
+            const float x = a.val[pos];
+            const f32x4 e = load4(a.E + (size_t)i * p, q, p);
+            acc += (e + d * x) * x;
+        }
+        // sum over the user slots of the wave (lanes with the same q)
+        for (int off = lpu; off < 64; off <<= 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[r] += __shfl_xor(acc[r], off);
+        }
+        red[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0 && lane < lpu && q < p) {
+            const f32x4 t = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+            *reinterpret_cast<f32x4 *>(a.partial + (size_t)gc * p + q) = t;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- reduce over chunks + normalise (one wave per atom) -----------------
+__global__ __launch_bounds__(256) void reduce_kernel(UpdateArgs a, int a0, int a1)
+{
+    const int p = a.p;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = a0 + blockIdx.x * 4 + wave;
+    if (j >= a1)
+        return;
+    const int c0 = a.chunk_ptr[j], c1 = a.chunk_ptr[j + 1];
+    float g[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int c = c0; c < c1; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = lane + 64 * r;
+            if (q < p)
+                g[r] += a.partial[(size_t)c * p + q];
+        }
+    float sq = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        sq += g[r] * g[r];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        sq += __shfl_xor(sq, off);
+    int state;
+    if (c1 == c0)
+        state = 1;  // no users: d_j unchanged
+    else if (!(sq > 0.f))
+        state = 2;  // F x^T = 0 (or not finite): unchanged
+    else
+        state = 0;
+    const float inv = state == 0 ? 1.0f / sqrtf(sq) : 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = lane + 64 * r;
+        if (q < p)
+            a.Dn[(size_t)j * p + q] = state == 0 ? g[r] * inv : a.D[(size_t)j * p + q];
+    }
+    if (lane == 0) {
+        a.atom_state[j] = state;
+        if (state == 1)
+            atomicAdd(&a.ctl->unused_atoms, 1ull);
+        else if (state == 2) {
+            atomicAdd(&a.ctl->zero_updates, 1ull);
+            if (!(sq == 0.f))
+                atomicAdd(&a.ctl->nonfinite, 1ull);
+        }
+    }
+}
+
+// ---- pass 2: AK-SVD representation refresh ------------------------------
+__global__ __launch_bounds__(256) void pass2_kernel(UpdateArgs a, int a0, int a1)
+{
+    const int p = a.p, s = a.s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lpu = lanes_per_user(p);
+    const int upw = 64 / lpu;
+    const int sub = lane / lpu;
+    const int q = 4 * (lane % lpu);
+    const int cbase = a.chunk_ptr[a0];
+    const int nch = a.chunk_ptr[a1] - cbase;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int gc = cbase + c;
+        const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
+        const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
+        const int u1 = min(u0 + kChunk, a.row_ptr[j + 1]);
+        const bool keep = a.rule != DL_RULE_AKSVD || a.atom_state[j] != 0;
+        const f32x4 d = load4(a.D + (size_t)j * p, q, p);
+        const f32x4 dn = load4(a.Dn + (size_t)j * p, q, p);
+        // every lane of the wave runs the same trip count (shuffles below)
+        for (int ub = u0 + wave * upw; ub < u1; ub += 4 * upw) {
+            const int u = ub + sub;
+            const bool on = u < u1;
+            float part = 0.f;
+            int pos = 0;
+            float x = 0.f;
+            if (on) {
+                pos = a.users[u];
+                x = a.val[pos];
+                if (!keep) {
+                    const f32x4 e = load4(a.E + (size_t)(pos / s) * p, q, p);
+                    const f32x4 f = e + d * x;
+                    part = f[0] * dn[0] + f[1] * dn[1] + f[2] * dn[2] + f[3] * dn[3];
+                }
+            }
+            for (int off = 1; off < lpu; off <<= 1)
+                part += __shfl_xor(part, off);
+            if (on && (lane % lpu) == 0)
+                a.valn[pos] = keep ? x : part;
+        }
+    }
+}
+
+// ---- incremental error update after a group (group sizes below n) -------
+// One lane group per entry of the group's CSR range; the entry that holds the
+// signal's first slot inside the group applies all of that signal's changes.
+__global__ __launch_bounds__(256) void eupdate_kernel(UpdateArgs a, int a0, int a1)
+{
+    const int p = a.p, s = a.s;
+    const int lane = threadIdx.x & 63;
+    const int lpu = lanes_per_user(p);
+    const int upw = 64 / lpu;
+    const int sub = lane / lpu;
+    const int q = 4 * (lane % lpu);
+    const int e0 = a.row_ptr[a0], e1 = a.row_ptr[a1];
+    const int wpg = blockDim.x >> 6;
+    const int wid = blockIdx.x * wpg + (threadIdx.x >> 6);
+    const int nw = gridDim.x * wpg;
+    for (int base = e0 + wid * upw; base < e1; base += nw * upw) {
+        const int u = base + sub;
+        if (u >= e1)
+            continue;
+        const int pos = a.users[u];
+        const int i = pos / s;
+        const int t0 = pos - i * s;
+        const int32_t *row = a.idx + (size_t)i * s;
+        bool first = true;
+        for (int t = 0; t < t0; ++t) {
+            const int jt = row[t];
+            if (jt >= a0 && jt < a1)
+                first = false;
+        }
+        if (!first || q >= p)
+            continue;
+        f32x4 e = *reinterpret_cast<const f32x4 *>(a.E + (size_t)i * p + q);
+        for (int t = t0; t < s; ++t) {
+            const int jt = row[t];
+            if (jt < a0 || jt >= a1)
+                continue;
+            const float xo = a.val[(size_t)i * s + t];
+            const float xn = a.valn[(size_t)i * s + t];
+            const f32x4 dold = *reinterpret_cast<const f32x4 *>(a.D + (size_t)jt * p + q);
+            const f32x4 dnew = *reinterpret_cast<const f32x4 *>(a.Dn + (size_t)jt * p + q);
+            e += dold * xo - dnew * xn;
+        }
+        *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e;
+    }
+}
+
+// ---- error ||Y - D X||_F^2 with an FP64 reduction ------------------------
+__global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
+{
+    __shared__ double red[256];
+    __shared__ bool am_last;
+    const int p = a.p, s = a.s;
+    const int lane = threadIdx.x & 63;
+    const int lpu = lanes_per_user(p);
+    const int upw = 64 / lpu;
+    const int sub = lane / lpu;
+    const int q = 4 * (lane % lpu);
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nw = gridDim.x * 4;
+    double acc = 0.0;
+    for (int i = wid * upw + sub; i < a.m; i += nw * upw) {
+        if (q >= p)
+            continue;
+        f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
+        for (int t = 0; t < s; ++t) {
+            const int j = a.idx[(size_t)i * s + t];
+            if (j < 0 || j >= a.n)
+                continue;
+            const float x = a.val[(size_t)i * s + t];
+            e -= *reinterpret_cast<const f32x4 *>(a.D + (size_t)j * p + q) * x;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc += (double)e[r] * (double)e[r];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.partial[blockIdx.x] = red[0];
+        __threadfence();
+        const unsigned prev = atomicAdd(&a.ctl->rmse_done, 1u);
+        am_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (am_last) {
+        __threadfence();
+        // fixed-order final sum over the blocks' partials
+        double v = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+            v += __hip_atomic_load(&a.partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double tot = red[0];
+            a.out[0] = sqrt(tot / ((double)a.p * (double)a.m));
+            if (!isfinite(tot))
+                atomicAdd(&a.ctl->nonfinite, 1ull);
+            a.ctl->rmse_done = 0;  // ready for the next call
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void residual_kernel(const float *__restrict__ Y,
+                                                       const float *__restrict__ D,
+                                                       const int32_t *__restrict__ idx,
+                                                       const float *__restrict__ val,
+                                                       float *__restrict__ E, int p, int n, int m,
+                                                       int s)
+{
+    const int lane = threadIdx.x & 63;
+    const int lpu = lanes_per_user(p);
+    const int upw = 64 / lpu;
+    const int sub = lane / lpu;
+    const int q = 4 * (lane % lpu);
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nw = gridDim.x * 4;
+    for (int i = wid * upw + sub; i < m; i += nw * upw) {
+        if (q >= p)
+            continue;
+        f32x4 e = *reinterpret_cast<const f32x4 *>(Y + (size_t)i * p + q);
+        for (int t = 0; t < s; ++t) {
+            const int j = idx[(size_t)i * s + t];
+            if (j < 0 || j >= n)
+                continue;
+            e -= *reinterpret_cast<const f32x4 *>(D + (size_t)j * p + q) * val[(size_t)i * s + t];
+        }
+        *reinterpret_cast<f32x4 *>(E + (size_t)i * p + q) = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void normalize_kernel(float *D, int n, int p, Control *ctl)
+{
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n)
+        return;
+    float v[4];
+    float sq = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = lane + 64 * r;
+        v[r] = q < p ? D[(size_t)j * p + q] : 0.f;
+        sq += v[r] * v[r];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        sq += __shfl_xor(sq, off);
+    if (!isfinite(sq) && lane == 0)
+        atomicAdd(&ctl->nonfinite, 1ull);
+    // zero atoms stay zero; atoms already of unit norm (to FP32 rounding) are
+    // left bit-for-bit as they are, so a run resumed from a saved dictionary
+    // continues exactly
+    if (!(sq > 0.f) || fabsf(sq - 1.0f) <= 4e-7f)
+        return;
+    const float inv = 1.0f / sqrtf(sq);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = lane + 64 * r;
+        if (q < p)
+            D[(size_t)j * p + q] = v[r] * inv;
+    }
+}
+
+__global__ void copy_kernel(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
+                            size_t words)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < words;
+         k += (size_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
+__global__ void zero_kernel(uint32_t *__restrict__ dst, size_t words)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < words;
+         k += (size_t)gridDim.x * blockDim.x)
+        dst[k] = 0u;
+}
+
+unsigned grid_for(size_t items, unsigned cap)
+{
+    size_t b = (items + 255) / 256;
+    if (b < 1)
+        b = 1;
+    return (unsigned)(b > cap ? cap : b);
+}
+
+}  // namespace
+
+int max_chunks(const dl_params &prm)
+{
+    const long long ms = (long long)prm.m * prm.s;
+    return (int)((ms + kChunk - 1) / kChunk) + prm.n;
+}
+
+hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
+{
+    const int gs = a.group_size >= a.n ? a.n : a.group_size;
+    for (int a0 = 0; a0 < a.n; a0 += gs) {
+        const int a1 = a0 + gs < a.n ? a0 + gs : a.n;
+        // upper bound of the group's chunks: each atom has at most m users
+        const long long users_ub = (long long)a.m * (a1 - a0) < (long long)a.m * a.s
+                                       ? (long long)a.m * (a1 - a0)
+                                       : (long long)a.m * a.s;
+        long long chunks_ub = (users_ub + kChunk - 1) / kChunk + (a1 - a0);
+        if (chunks_ub > a.max_chunks)
+            chunks_ub = a.max_chunks;
+        const unsigned grid = (unsigned)(chunks_ub > 2048 ? 2048 : (chunks_ub < 1 ? 1 : chunks_ub));
+        hipLaunchKernelGGL(pass1_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(reduce_kernel, dim3((a1 - a0 + 3) / 4), dim3(256), 0, st, a, a0, a1);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(pass2_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        if (a1 < a.n) {
+            const unsigned eg = grid_for((size_t)users_ub * 16, 2048);
+            hipLaunchKernelGGL(eupdate_kernel, dim3(eg), dim3(256), 0, st, a, a0, a1);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_rmse(const RmseArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(rmse_kernel, dim3(kRmseBlocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const float *Y, const float *D, const int32_t *idx, const float *val,
+                           float *E, int p, int n, int m, int s, hipStream_t st)
+{
+    hipLaunchKernelGGL(residual_kernel, dim3(grid_for((size_t)m * 16, 4096)), dim3(256), 0, st, Y,
+                       D, idx, val, E, p, n, m, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize_rows(float *D, int n, int p, Control *ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(normalize_kernel, dim3((n + 3) / 4), dim3(256), 0, st, D, n, p, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
+{
+    const size_t words = bytes / 4;  // every buffer here is a multiple of 4 bytes
+    if (words == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(words, 4096)), dim3(256), 0, st,
+                       (const uint32_t *)src, (uint32_t *)dst, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *dst, size_t bytes, hipStream_t st)
+{
+    const size_t words = bytes / 4;
+    if (words == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(words, 4096)), dim3(256), 0, st,
+                       (uint32_t *)dst, words);
+    return hipGetLastError();
+}
+
+}  // namespace dlk

@@ -1,0 +1,195 @@
+"""Python binding of the C ABI in ``include/dl.h`` (argument marshalling only).
+
+Every function here passes device pointers of torch tensors and the current
+HIP stream to the library ``libdl_mi355.so``; all arithmetic runs in the HIP
+kernels.  If the library has not been built the first call raises: there is
+no other implementation to fall back to.
+
+Layouts (row-major): D ``[n][p]`` float32, Y ``[m][p]`` float32,
+X_idx ``[m][s]`` int32 (-1 = unused slot), X_val ``[m][s]`` float32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdl_mi355.so")
+
+DL_OK, DL_EINVAL, DL_EWORKSPACE, DL_EHIP, DL_ENUMERIC, DL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PREC_FP32, PREC_BF16 = 0, 1
+RULE_AKSVD, RULE_SGK = 0, 1
+
+
+class DLError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int), ("n", ctypes.c_int), ("m", ctypes.c_int), ("s", ctypes.c_int),
+        ("group_size", ctypes.c_int), ("precision", ctypes.c_int), ("rule", ctypes.c_int),
+        ("pivot_fp64_threshold", ctypes.c_float), ("tol_corr", ctypes.c_float),
+        ("tol_pivot", ctypes.c_float),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("fp64_pivot_recomputes", ctypes.c_longlong), ("early_stops", ctypes.c_longlong),
+        ("unused_atoms", ctypes.c_longlong), ("zero_updates", ctypes.c_longlong),
+        ("nonfinite", ctypes.c_longlong), ("fallbacks", ctypes.c_longlong),
+    ]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_PP = ctypes.POINTER(_Params)
+
+# name -> (restype, argtypes); the same list is checked against the header by the tests
+SIGNATURES = {
+    "dl_abi_version": (ctypes.c_int, []),
+    "dl_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "dl_params_default": (ctypes.c_int, [_PP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "dl_workspace_size": (ctypes.c_size_t, [_PP]),
+    "dl_workspace_init": (ctypes.c_int, [_PP, _vp, ctypes.c_size_t, _vp]),
+    "dl_gram": (ctypes.c_int, [_PP, _vp, _vp, _vp]),
+    "dl_corr": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp]),
+    "dl_omp": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "dl_csr": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "dl_jau_update": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "dl_rmse": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "dl_iterate": (ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                  ctypes.c_size_t, _vp]),
+    "dl_read_stats": (ctypes.c_int, [_PP, _vp, ctypes.c_size_t, ctypes.POINTER(Stats), _vp]),
+}
+
+
+def lib():
+    """Load ``libdl_mi355.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1509_05054_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return lib().dl_status_string(int(status)).decode()
+    except Exception:  # library missing: still report the number
+        return f"status {status}"
+
+
+def _check(status: int, what: str):
+    if status != DL_OK:
+        raise DLError(status, what)
+
+
+@dataclass
+class Params:
+    p: int
+    n: int
+    m: int
+    s: int
+    group_size: int | None = None
+    precision: int = PREC_FP32
+    rule: int = RULE_AKSVD
+    pivot_fp64_threshold: float = 1e-6
+    tol_corr: float = 1e-5
+    tol_pivot: float = 1e-10
+
+    def c(self) -> _Params:
+        return _Params(self.p, self.n, self.m, self.s,
+                       self.n if self.group_size is None else self.group_size,
+                       self.precision, self.rule, self.pivot_fp64_threshold, self.tol_corr,
+                       self.tol_pivot)
+
+    def ref(self):
+        self._c = self.c()  # keep alive for the call
+        return ctypes.byref(self._c)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def workspace_size(prm: Params) -> int:
+    n = lib().dl_workspace_size(prm.ref())
+    if n == 0:
+        raise DLError(DL_EINVAL, "dl_workspace_size")
+    return int(n)
+
+
+def workspace(prm: Params, device="cuda") -> torch.Tensor:
+    """Allocate (torch caching allocator) and initialise a workspace for ``prm``."""
+    ws = torch.empty(workspace_size(prm), dtype=torch.uint8, device=device)
+    _check(lib().dl_workspace_init(prm.ref(), _ptr(ws), ws.numel(), _stream()), "dl_workspace_init")
+    return ws
+
+
+def gram(prm: Params, D, G, stream=None):
+    _check(lib().dl_gram(prm.ref(), _ptr(D), _ptr(G), _stream(stream)), "dl_gram")
+
+
+def corr(prm: Params, D, Y, A0, stream=None):
+    _check(lib().dl_corr(prm.ref(), _ptr(D), _ptr(Y), _ptr(A0), _stream(stream)), "dl_corr")
+
+
+def omp(prm: Params, D, Y, X_idx, X_val, ws, stream=None):
+    _check(lib().dl_omp(prm.ref(), _ptr(D), _ptr(Y), _ptr(X_idx), _ptr(X_val), _ptr(ws),
+                        ws.numel(), _stream(stream)), "dl_omp")
+
+
+def csr(prm: Params, X_idx, row_ptr, users, ws, stream=None):
+    _check(lib().dl_csr(prm.ref(), _ptr(X_idx), _ptr(row_ptr), _ptr(users), _ptr(ws),
+                        ws.numel(), _stream(stream)), "dl_csr")
+
+
+def jau_update(prm: Params, Y, D, X_idx, X_val, ws, stream=None):
+    _check(lib().dl_jau_update(prm.ref(), _ptr(Y), _ptr(D), _ptr(X_idx), _ptr(X_val), _ptr(ws),
+                               ws.numel(), _stream(stream)), "dl_jau_update")
+
+
+def rmse(prm: Params, Y, D, X_idx, X_val, out, ws, stream=None):
+    _check(lib().dl_rmse(prm.ref(), _ptr(Y), _ptr(D), _ptr(X_idx), _ptr(X_val), _ptr(out),
+                         _ptr(ws), ws.numel(), _stream(stream)), "dl_rmse")
+
+
+def iterate(prm: Params, Y, D, iters, X_idx, X_val, rmse_out, ws, stream=None):
+    _check(lib().dl_iterate(prm.ref(), _ptr(Y), _ptr(D), int(iters), _ptr(X_idx), _ptr(X_val),
+                            _ptr(rmse_out), _ptr(ws), ws.numel(), _stream(stream)), "dl_iterate")
+
+
+def read_stats(prm: Params, ws, stream=None, allow_nonfinite=False) -> dict:
+    st = Stats()
+    rc = lib().dl_read_stats(prm.ref(), _ptr(ws), ws.numel(), ctypes.byref(st), _stream(stream))
+    if rc == DL_ENUMERIC and allow_nonfinite:
+        return st.as_dict()
+    _check(rc, "dl_read_stats")
+    return st.as_dict()
