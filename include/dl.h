@@ -70,6 +70,14 @@ typedef struct dl_params {
     float pivot_fp64_threshold;   /* FP32 Cholesky pivots below this are recomputed in FP64 (1e-6) */
     float tol_corr;               /* OMP stops when max |d_j^T r| <= tol_corr * ||y|| (1e-5) */
     float tol_pivot;              /* OMP stops when the FP64 pivot <= tol_pivot * G_jj (1e-10) */
+    /* Launch shape of the OMP kernel (0 = default).  A signal is coded by
+       omp_lanes_per_signal lanes (4, 8, 16, 32 or 64) each holding
+       omp_atoms_per_lane correlations (16, or 8 with 8+ lanes); their product
+       must be >= n.  Only the launch shape changes: every value is computed
+       with the same operations, except the summation order of ||y|| in the
+       stop test. */
+    int omp_lanes_per_signal;
+    int omp_atoms_per_lane;
 } dl_params;
 
 /* Counters kept in the workspace (device); read them with dl_read_stats. */
@@ -149,6 +157,35 @@ dl_status dl_rmse(const dl_params *prm, const float *Y, const float *D, const in
    first. */
 dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, int32_t *X_idx,
                      float *X_val, double *rmse, void *ws, size_t ws_bytes, dl_stream_t stream);
+
+/* Kernels the library launches, for dl_profile_read. */
+typedef enum {
+    DL_K_GRAM = 0,      /* G = D D^T */
+    DL_K_CORR,          /* A0 = Y D^T */
+    DL_K_OMP,           /* per-signal OMP */
+    DL_K_CSR_COUNT,     /* users of every atom: per-block counts */
+    DL_K_CSR_SCAN,      /* users of every atom: offsets */
+    DL_K_CSR_SCATTER,   /* users of every atom: placement */
+    DL_K_UPD_PASS1,     /* F x^T per chunk of users */
+    DL_K_UPD_REDUCE,    /* sum over chunks and normalisation */
+    DL_K_UPD_PASS2,     /* AK-SVD refresh of X */
+    DL_K_UPD_EUPDATE,   /* error update between groups */
+    DL_K_RMSE,          /* error with the FP64 reduction */
+    DL_K_MISC,          /* casts, copies, normalisation, residual */
+    DL_K_COUNT
+} dl_kernel;
+
+/* Measurement support.  While enabled, every kernel launch of the library is
+   bracketed by two HIP events recorded on the launch's own stream (the
+   caller's), so that per-kernel GPU time can be read back.  Host-side state,
+   not thread-safe; at most `max_launches` launches are recorded (later ones
+   are not timed).  on = 0 disables and discards recorded events. */
+dl_status dl_profile_enable(int on, int max_launches);
+
+/* Wait for the recorded events, add each kernel's total time (ms) and launch
+   count into ms[k] / launches[k] for k < count (count <= DL_K_COUNT), then
+   clear the record (timing stays enabled). */
+dl_status dl_profile_read(double *ms, long long *launches, int count);
 
 /* Synchronise `stream` and copy the workspace counters to *out (host).
    Returns DL_ENUMERIC if any non-finite value was counted, else DL_OK. */

@@ -70,6 +70,8 @@ def _load():
         lib.dlo_iterate.argtypes = [c_int, c_int, c_int, c_int, dp, dp, c_int, c_int, c_int,
                                     c_double, c_double, ip, dp, dp]
         lib.dlo_iterate.restype = None
+        lib.dlo_max_threads.argtypes = []
+        lib.dlo_max_threads.restype = c_int
         _lib = lib
     return _lib
 
@@ -140,6 +142,11 @@ def jau_update(Y, D, idx, val, group_size, rule=RULE_AKSVD, atoms=None):
     unused = lib.dlo_jau_update_range(p, n, m, s, _dp(Y), _dp(D), _ip(idx), _dp(val),
                                       int(group_size), int(rule), int(a0), int(a1))
     return D, val, int(unused)
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().dlo_max_threads())
 
 
 def normalize(D):

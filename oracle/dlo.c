@@ -25,6 +25,7 @@
  *   - The error is measured after the atom update, with the refreshed X.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -332,3 +333,6 @@ void dlo_iterate(int p, int n, int m, int s, const double *Y, double *D, int ite
         rmse[k] = dlo_rmse(p, m, s, Y, D, idx, val);
     }
 }
+
+/* Threads the oracle's parallel loops use. */
+int dlo_max_threads(void) { return omp_get_max_threads(); }

@@ -22,20 +22,22 @@ Layout layout_for(const dl_params &prm)
         return at;
     };
     L.control = take(sizeof(Control));
-    L.G = take(sizeof(float) * n * n);
-    L.A0 = take(sizeof(float) * m * n);
+    const size_t ldn = (size_t)padded_n(prm.n);
+    L.G = take(sizeof(float) * n * ldn);
+    L.A0 = take(sizeof(float) * m * ldn);
     L.E = take(sizeof(float) * m * p);
     L.Dn = take(sizeof(float) * n * p);
     L.val_ws = take(sizeof(float) * m * s);
     L.valn = take(sizeof(float) * m * s);
     L.blkcnt = take(sizeof(int32_t) * nb * n);
     L.lrank = take(sizeof(int32_t) * m * s);
+    L.atom_tot = take(sizeof(int32_t) * n);
     L.row_ptr = take(sizeof(int32_t) * (n + 1));
     L.chunk_ptr = take(sizeof(int32_t) * (n + 1));
     L.users = take(sizeof(int32_t) * m * s);
     L.atom_state = take(sizeof(int32_t) * n);
     L.partial = take(sizeof(float) * (size_t)max_chunks(prm) * p);
-    L.rmse_part = take(sizeof(double) * kRmseBlocks);
+    L.rmse_part = take(sizeof(double) * (size_t)rmse_blocks(prm.m));
     if (prm.precision == DL_PREC_BF16) {
         L.Dbf = take(sizeof(uint16_t) * n * p);
         L.Ybf = take(sizeof(uint16_t) * m * p);
@@ -75,6 +77,13 @@ bool valid_params(const dl_params *prm)
         return false;
     if (!(q.pivot_fp64_threshold >= 0.f) || !(q.tol_corr >= 0.f) || !(q.tol_pivot >= 0.f))
         return false;
+    if (q.omp_lanes_per_signal != 0 || q.omp_atoms_per_lane != 0) {
+        const int npl = q.omp_atoms_per_lane ? q.omp_atoms_per_lane : 16;
+        const int lps = q.omp_lanes_per_signal ? q.omp_lanes_per_signal
+                                               : omp_lanes_per_signal(q.n, npl);
+        if (!omp_config_ok(q.n, lps, npl))
+            return false;
+    }
     return true;
 }
 
@@ -106,24 +115,24 @@ dl_status check_ws(const dl_params *prm, const void *ws, size_t ws_bytes, Ws *ou
             return DL_EHIP;                        \
     } while (0)
 
-// G and A0 for the coding stage, in the precision the parameters ask for.
+// G and A0 for the coding stage in one launch, in the precision the
+// parameters ask for.
 dl_status products(const dl_params &prm, const float *D, const float *Y, float *G, float *A0,
                    const Ws *ws, hipStream_t st)
 {
+    const int ldn = padded_n(prm.n);
     if (prm.precision == DL_PREC_BF16) {
         uint16_t *Dbf = ws->at<uint16_t>(ws->L.Dbf);
         uint16_t *Ybf = ws->at<uint16_t>(ws->L.Ybf);
         DL_TRY(launch_cast_bf16(D, Dbf, (size_t)prm.n * prm.p, st));
         DL_TRY(launch_cast_bf16(Y, Ybf, (size_t)prm.m * prm.p, st));
-        if (G)
-            DL_TRY(launch_gemm_nt_bf16(Dbf, Dbf, G, prm.n, prm.n, prm.p, st));
-        if (A0)
-            DL_TRY(launch_gemm_nt_bf16(Ybf, Dbf, A0, prm.m, prm.n, prm.p, st));
+        const GemmBF16 g{Dbf, Dbf, G, prm.n, prm.n, prm.p, ldn};
+        const GemmBF16 c{Ybf, Dbf, A0, prm.m, prm.n, prm.p, ldn};
+        DL_TRY(launch_gemm_nt_bf16(g, &c, DL_K_CORR, st));
     } else {
-        if (G)
-            DL_TRY(launch_gemm_nt_f32(D, D, G, prm.n, prm.n, prm.p, st));
-        if (A0)
-            DL_TRY(launch_gemm_nt_f32(Y, D, A0, prm.m, prm.n, prm.p, st));
+        const GemmF32 g{D, D, G, prm.n, prm.n, prm.p, ldn};
+        const GemmF32 c{Y, D, A0, prm.m, prm.n, prm.p, ldn};
+        DL_TRY(launch_gemm_nt_f32(g, &c, DL_K_CORR, st));
     }
     return DL_OK;
 }
@@ -149,6 +158,9 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
     a.n = prm.n;
     a.m = prm.m;
     a.s = prm.s;
+    a.ldn = padded_n(prm.n);
+    a.lanes_per_signal = prm.omp_lanes_per_signal;
+    a.atoms_per_lane = prm.omp_atoms_per_lane;
     a.pivot_fp64 = prm.pivot_fp64_threshold;
     a.tol_corr = prm.tol_corr;
     a.tol_pivot = prm.tol_pivot;
@@ -162,6 +174,8 @@ dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, in
     CsrArgs c;
     c.idx = idx;
     c.blkcnt = ws.at<int32_t>(ws.L.blkcnt);
+    c.tot = ws.at<int32_t>(ws.L.atom_tot);
+    c.ctl = ws.ctl();
     c.lrank = ws.at<int32_t>(ws.L.lrank);
     c.row_ptr = row_ptr;
     c.chunk_ptr = ws.at<int32_t>(ws.L.chunk_ptr);
@@ -291,7 +305,8 @@ dl_status dl_gram(const dl_params *prm, const float *D, float *G, dl_stream_t st
         return DL_EINVAL;
     if (prm->precision != DL_PREC_FP32)
         return DL_EUNSUPPORTED;  // the BF16 product needs the workspace: use dl_omp
-    DL_TRY(launch_gemm_nt_f32(D, D, G, prm->n, prm->n, prm->p, (hipStream_t)stream));
+    const GemmF32 g{D, D, G, prm->n, prm->n, prm->p, prm->n};
+    DL_TRY(launch_gemm_nt_f32(g, nullptr, DL_K_GRAM, (hipStream_t)stream));
     return DL_OK;
 }
 
@@ -302,7 +317,8 @@ dl_status dl_corr(const dl_params *prm, const float *D, const float *Y, float *A
         return DL_EINVAL;
     if (prm->precision != DL_PREC_FP32)
         return DL_EUNSUPPORTED;
-    DL_TRY(launch_gemm_nt_f32(Y, D, A0, prm->m, prm->n, prm->p, (hipStream_t)stream));
+    const GemmF32 c{Y, D, A0, prm->m, prm->n, prm->p, prm->n};
+    DL_TRY(launch_gemm_nt_f32(c, nullptr, DL_K_CORR, (hipStream_t)stream));
     return DL_OK;
 }
 

@@ -1,16 +1,17 @@
 // Users of every atom (the set I_j of Sec. 3): a deterministic, stable
 // counting-sort transpose of the ELL representation X into CSR by atom.
 //
-//   count   : one workgroup per block of kCsrBlock signals.  Each wave walks
-//             its 64 signals' entries in (signal, slot) order, 64 at a time;
-//             entries of one atom inside a 64-entry chunk are ranked with a
-//             ballot loop, and per-wave running counts (LDS) rank them across
-//             chunks.  Result: per-block atom counts and, per entry, its rank
-//             among the block's uses of that atom.
-//   scan    : one workgroup; per atom, totals over blocks, an exclusive scan
-//             over atoms (row_ptr, and chunk_ptr for the update's chunks of
-//             kChunk users), then the per-(block, atom) start offsets.
-//   scatter : one thread per entry: users[offset(block, atom) + rank] = entry.
+//   count   : one workgroup per block of kCsrBlock signals, one wave per 64
+//             signals.  A wave walks its entries in (signal, slot) order, 64
+//             at a time; each lane sets its bit in an LDS bit mask of its
+//             atom, so its rank among the chunk's uses of that atom is the
+//             popcount of the lower bits, and per-wave running counts rank
+//             the chunks.  Result: per-(atom, block) counts and, per entry,
+//             its rank among the block's uses of the atom.
+//   scan    : one wave per atom scans its per-block counts into offsets; the
+//             last workgroup to finish scans the atom totals into row_ptr
+//             (and chunk_ptr, the update's chunks of kChunk users).
+//   scatter : one thread per entry: users[row_ptr + offset + rank] = entry.
 // Entries of an atom end up in increasing (signal, slot) order, so the
 // result is unique and the atom update's summation order is fixed.
 #include "dl_internal.h"
@@ -30,19 +31,25 @@ __device__ inline void wave_lds_sync()
 __global__ __launch_bounds__(kCsrBlock) void csr_count_kernel(const int32_t *__restrict__ idx,
                                                               int32_t *__restrict__ blkcnt,
                                                               int32_t *__restrict__ lrank, int n,
-                                                              int m, int s)
+                                                              int m, int s, int nb)
 {
-    extern __shared__ int32_t wcnt[];  // [kWavesPerBlock][n]
+    extern __shared__ unsigned long long smem[];
+    unsigned long long *masks = smem;                                  // [waves][n]
+    int32_t *wcnt = reinterpret_cast<int32_t *>(smem + kWavesPerBlock * n);  // [waves][n]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int b = blockIdx.x;
-    for (int t = threadIdx.x; t < kWavesPerBlock * n; t += blockDim.x)
+    for (int t = threadIdx.x; t < kWavesPerBlock * n; t += blockDim.x) {
+        masks[t] = 0ull;
         wcnt[t] = 0;
+    }
     __syncthreads();
 
+    unsigned long long *mymask = masks + wave * n;
     int32_t *mycnt = wcnt + wave * n;
     const int sig0 = b * kCsrBlock + wave * 64;
-    const unsigned long long lt = (1ull << lane) - 1ull;
+    const unsigned long long bit = 1ull << lane;
+    const unsigned long long lower = bit - 1ull;
     for (int c = 0; c < s; ++c) {
         const int e = 64 * c + lane;  // entry inside this wave's 64 x s block
         const int i = sig0 + e / s;
@@ -50,28 +57,21 @@ __global__ __launch_bounds__(kCsrBlock) void csr_count_kernel(const int32_t *__r
         int atom = i < m ? idx[(size_t)i * s + t] : -1;
         if (atom >= n)
             atom = -1;  // out-of-range indices are treated as unused slots
-        unsigned long long pending = __ballot(atom >= 0);
-        int myrank = 0, mycount = 0;
-        bool last = false;
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int la = __builtin_amdgcn_readlane(atom, leader);
-            const unsigned long long mm = __ballot(atom == la);
-            if (atom == la) {
-                myrank = __popcll(mm & lt);
-                mycount = __popcll(mm);
-                last = lane == 63 - __clzll((long long)mm);
-            }
-            pending &= ~mm;
-        }
+        if (atom >= 0)
+            atomicOr(&mymask[atom], bit);
+        wave_lds_sync();
+        unsigned long long mm = 0;
         int base = 0;
         if (atom >= 0) {
+            mm = mymask[atom];
             base = mycnt[atom];
-            lrank[(size_t)i * s + t] = base + myrank;
+            lrank[(size_t)i * s + t] = base + __popcll(mm & lower);
         }
         wave_lds_sync();
-        if (atom >= 0 && last)
-            mycnt[atom] = base + mycount;
+        if (atom >= 0 && lane == 63 - __clzll((long long)mm)) {
+            mycnt[atom] = base + __popcll(mm);
+            mymask[atom] = 0ull;
+        }
         wave_lds_sync();
     }
     __syncthreads();
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kCsrBlock) void csr_count_kernel(const int32_t *__r
             wcnt[w * n + a] = run;
             run += v;
         }
-        blkcnt[(size_t)b * n + a] = run;
+        blkcnt[(size_t)a * nb + b] = run;
     }
     __syncthreads();
     for (int c = 0; c < s; ++c) {
@@ -98,74 +98,105 @@ __global__ __launch_bounds__(kCsrBlock) void csr_count_kernel(const int32_t *__r
     }
 }
 
-// Exclusive scan of one value per thread over a 1024-thread workgroup;
-// returns the exclusive prefix and writes the workgroup total to *total.
-__device__ int block_exclusive_scan(int v, int *sh /*[16]*/, int *total)
+__device__ inline int wave_inclusive_scan(int x)
 {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    int x = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const int y = __shfl_up(x, off);
         if (lane >= off)
             x += y;
     }
-    if (lane == 63)
-        sh[wave] = x;
-    __syncthreads();
-    int wbase = 0, tot = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        const int t = sh[w];
-        if (w < wave)
-            wbase += t;
-        tot += t;
-    }
-    __syncthreads();
-    *total = tot;
-    return wbase + x - v;
+    return x;
 }
 
-__global__ __launch_bounds__(1024) void csr_scan_kernel(int32_t *__restrict__ blkcnt,
-                                                        int32_t *__restrict__ row_ptr,
-                                                        int32_t *__restrict__ chunk_ptr, int n,
-                                                        int nb)
+// Per atom: per-block counts -> offsets inside the atom's user list, and the
+// atom total.  The last workgroup scans the totals into row_ptr / chunk_ptr.
+__global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blkcnt,
+                                                       int32_t *__restrict__ tot,
+                                                       int32_t *__restrict__ row_ptr,
+                                                       int32_t *__restrict__ chunk_ptr,
+                                                       Control *ctl, int n, int nb)
 {
-    __shared__ int sh[16];
-    int carry_u = 0, carry_c = 0;
-    for (int a0 = 0; a0 < n; a0 += blockDim.x) {
-        const int a = a0 + threadIdx.x;
-        int tot = 0;
-        if (a < n)
-            for (int b = 0; b < nb; ++b)
-                tot += blkcnt[(size_t)b * n + a];
-        const int chunks = (tot + kChunk - 1) / kChunk;
-        int tu, tc;
-        const int pu = block_exclusive_scan(tot, sh, &tu) + carry_u;
-        const int pc = block_exclusive_scan(chunks, sh, &tc) + carry_c;
-        if (a < n) {
-            row_ptr[a] = pu;
-            chunk_ptr[a] = pc;
-            int run = pu;
-            for (int b = 0; b < nb; ++b) {
-                const int v = blkcnt[(size_t)b * n + a];
-                blkcnt[(size_t)b * n + a] = run;
-                run += v;
-            }
+    __shared__ int sh[2][4];
+    __shared__ bool am_last;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int a = blockIdx.x * 4 + wave;
+    if (a < n) {
+        int carry = 0;
+        for (int b0 = 0; b0 < nb; b0 += 64) {
+            const int b = b0 + lane;
+            const int v = b < nb ? blkcnt[(size_t)a * nb + b] : 0;
+            const int x = wave_inclusive_scan(v);
+            if (b < nb)
+                blkcnt[(size_t)a * nb + b] = carry + x - v;
+            carry += __shfl(x, 63);
         }
-        carry_u += tu;
-        carry_c += tc;
+        if (lane == 0)
+            tot[a] = carry;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&ctl->csr_done, 1u);
+        am_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!am_last)
+        return;
+    __threadfence();
+    // exclusive scan of the atom totals: thread t owns atoms [t*per, (t+1)*per)
+    const int per = (n + 255) / 256;
+    const int a0 = threadIdx.x * per;
+    int su = 0, sc = 0;
+    for (int q = 0; q < per; ++q) {
+        const int aa = a0 + q;
+        if (aa < n) {
+            const int v = __hip_atomic_load(&tot[aa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            su += v;
+            sc += (v + kChunk - 1) / kChunk;
+        }
+    }
+    const int xu = wave_inclusive_scan(su);
+    const int xc = wave_inclusive_scan(sc);
+    if (lane == 63) {
+        sh[0][wave] = xu;
+        sh[1][wave] = xc;
+    }
+    __syncthreads();
+    int bu = 0, bc = 0, tu = 0, tc = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wave) {
+            bu += sh[0][w];
+            bc += sh[1][w];
+        }
+        tu += sh[0][w];
+        tc += sh[1][w];
+    }
+    int ru = bu + xu - su, rc = bc + xc - sc;
+    for (int q = 0; q < per; ++q) {
+        const int aa = a0 + q;
+        if (aa < n) {
+            const int v = __hip_atomic_load(&tot[aa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            row_ptr[aa] = ru;
+            chunk_ptr[aa] = rc;
+            ru += v;
+            rc += (v + kChunk - 1) / kChunk;
+        }
     }
     if (threadIdx.x == 0) {
-        row_ptr[n] = carry_u;
-        chunk_ptr[n] = carry_c;
+        row_ptr[n] = tu;
+        chunk_ptr[n] = tc;
+        ctl->csr_done = 0;  // ready for the next call
     }
 }
 
 __global__ void csr_scatter_kernel(const int32_t *__restrict__ idx,
                                    const int32_t *__restrict__ blkoff,
+                                   const int32_t *__restrict__ row_ptr,
                                    const int32_t *__restrict__ lrank, int32_t *__restrict__ users,
-                                   float *__restrict__ val_pad, int n, int m, int s)
+                                   float *__restrict__ val_pad, int n, int m, int s, int nb)
 {
     const size_t total = (size_t)m * s;
     for (size_t pos = (size_t)blockIdx.x * blockDim.x + threadIdx.x; pos < total;
@@ -177,7 +208,7 @@ __global__ void csr_scatter_kernel(const int32_t *__restrict__ idx,
             continue;
         }
         const int b = (int)(pos / s) / kCsrBlock;
-        users[blkoff[(size_t)b * n + atom] + lrank[pos]] = (int32_t)pos;
+        users[row_ptr[atom] + blkoff[(size_t)atom * nb + b] + lrank[pos]] = (int32_t)pos;
     }
 }
 
@@ -188,14 +219,18 @@ int csr_blocks(int m) { return (m + kCsrBlock - 1) / kCsrBlock; }
 hipError_t launch_csr(const CsrArgs &a, hipStream_t st)
 {
     const int nb = csr_blocks(a.m);
-    const size_t shmem = sizeof(int32_t) * kWavesPerBlock * a.n;
+    const size_t shmem = (sizeof(unsigned long long) + sizeof(int32_t)) * kWavesPerBlock * a.n;
+    prof_begin(DL_K_CSR_COUNT, st);
     hipLaunchKernelGGL(csr_count_kernel, dim3(nb), dim3(kCsrBlock), shmem, st, a.idx, a.blkcnt,
-                       a.lrank, a.n, a.m, a.s);
+                       a.lrank, a.n, a.m, a.s, nb);
+    prof_end(DL_K_CSR_COUNT, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(csr_scan_kernel, dim3(1), dim3(1024), 0, st, a.blkcnt, a.row_ptr,
-                       a.chunk_ptr, a.n, nb);
+    prof_begin(DL_K_CSR_SCAN, st);
+    hipLaunchKernelGGL(csr_scan_kernel, dim3((a.n + 3) / 4), dim3(256), 0, st, a.blkcnt, a.tot,
+                       a.row_ptr, a.chunk_ptr, a.ctl, a.n, nb);
+    prof_end(DL_K_CSR_SCAN, st);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -203,8 +238,10 @@ hipError_t launch_csr(const CsrArgs &a, hipStream_t st)
     size_t blocks = (total + 255) / 256;
     if (blocks > 8192)
         blocks = 8192;
+    prof_begin(DL_K_CSR_SCATTER, st);
     hipLaunchKernelGGL(csr_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a.idx,
-                       a.blkcnt, a.lrank, a.users, a.val_pad, a.n, a.m, a.s);
+                       a.blkcnt, a.row_ptr, a.lrank, a.users, a.val_pad, a.n, a.m, a.s, nb);
+    prof_end(DL_K_CSR_SCATTER, st);
     return hipGetLastError();
 }
 

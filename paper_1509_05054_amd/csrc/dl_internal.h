@@ -14,8 +14,8 @@ namespace dlk {
 constexpr int kChunk = 256;
 // Signals per block of the CSR transpose (one workgroup each).
 constexpr int kCsrBlock = 256;
-// Workgroups of the FP64 error reduction.
-constexpr int kRmseBlocks = 512;
+// Signals per workgroup of the FP64 error reduction.
+constexpr int kRmseSignals = 64;
 
 // Device-side counters and control words at the start of the workspace.
 struct Control {
@@ -26,7 +26,8 @@ struct Control {
     unsigned long long nonfinite;
     unsigned long long fallbacks;
     unsigned int rmse_done;  // arrival counter of the error reduction (self-resetting)
-    unsigned int pad[15];
+    unsigned int csr_done;   // arrival counter of the CSR offset scan (self-resetting)
+    unsigned int pad[14];
 };
 
 // Byte offsets of the workspace regions (each 256-byte aligned).
@@ -38,14 +39,15 @@ struct Layout {
     size_t Dn;         // [n][p] float, next dictionary
     size_t val_ws;     // [m][s] float, OMP coefficients before the update
     size_t valn;       // [m][s] float, refreshed coefficients (dl_jau_update)
-    size_t blkcnt;     // [nb][n] int, per-block atom counts, then offsets
+    size_t blkcnt;     // [n][nb] int, per-(atom, block) counts, then offsets
     size_t lrank;      // [m*s] int, rank of an entry among its block's uses of the atom
+    size_t atom_tot;   // [n] int, users per atom
     size_t row_ptr;    // [n+1] int
     size_t chunk_ptr;  // [n+1] int
     size_t users;      // [m*s] int
     size_t atom_state; // [n] int: 0 updated, 1 no users, 2 zero F x^T
     size_t partial;    // [max_chunks][p] float
-    size_t rmse_part;  // [kRmseBlocks] double
+    size_t rmse_part;  // [rmse_blocks(m)] double
     size_t Dbf;        // [n][p] bf16 (precision variant)
     size_t Ybf;        // [m][p] bf16 (precision variant)
     size_t total;
@@ -54,14 +56,27 @@ struct Layout {
 Layout layout_for(const dl_params &prm);
 int csr_blocks(int m);
 int max_chunks(const dl_params &prm);
+int rmse_blocks(int m);
+
+// Optional per-kernel timing (dl_profile_enable): bracket a launch.
+void prof_begin(int kernel, hipStream_t st);
+void prof_end(int kernel, hipStream_t st);
 
 // ---- launchers (return hipSuccess or the launch error) -------------------
-// C[M][N] = A[M][K] * B[N][K]^T, FP32 inputs, FP32 accumulation on MFMA.
-hipError_t launch_gemm_nt_f32(const float *A, const float *B, float *C, int M, int N, int K,
-                              hipStream_t st);
-// Same with BF16 inputs (uint16 bit patterns).
-hipError_t launch_gemm_nt_bf16(const uint16_t *A, const uint16_t *B, float *C, int M, int N,
-                               int K, hipStream_t st);
+// C[M][N] (row stride ldc) = A[M][K] * B[N][K]^T on MFMA with FP32
+// accumulation; K % 4 == 0.  Up to two independent problems share a launch.
+struct GemmF32 {
+    const float *A, *B;
+    float *C;
+    int M, N, K, ldc;
+};
+struct GemmBF16 {  // BF16 inputs as uint16 bit patterns
+    const uint16_t *A, *B;
+    float *C;
+    int M, N, K, ldc;
+};
+hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st);
+hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st);
 // Round FP32 to BF16 (nearest even).
 hipError_t launch_cast_bf16(const float *x, uint16_t *y, size_t count, hipStream_t st);
 
@@ -75,13 +90,22 @@ struct OmpArgs {
     float *E;          // [m][p] residual, may be null
     Control *ctl;
     int p, n, m, s;
+    int ldn;               // leading dimension of G and A0 rows (multiple of 4, >= n)
+    int lanes_per_signal;  // 4..64, or 0 for the default
+    int atoms_per_lane;    // 8 or 16, or 0 for the default (16)
     float pivot_fp64, tol_corr, tol_pivot;
 };
 hipError_t launch_omp(const OmpArgs &a, hipStream_t st);
+int omp_lanes_per_signal(int n, int npl);
+bool omp_config_ok(int n, int lps, int npl);
+// Leading dimension used for G and A0 rows.
+inline int padded_n(int n) { return (n + 3) & ~3; }
 
 struct CsrArgs {
     const int32_t *idx;  // [m][s]
-    int32_t *blkcnt;     // [nb][n]
+    int32_t *blkcnt;     // [n][nb] per-(atom, block) counts, then offsets
+    int32_t *tot;        // [n] users per atom
+    Control *ctl;
     int32_t *lrank;      // [m*s]
     int32_t *row_ptr;    // [n+1]
     int32_t *chunk_ptr;  // [n+1]
@@ -111,7 +135,7 @@ struct RmseArgs {
     const float *Y, *D;
     const int32_t *idx;
     const float *val;
-    double *partial;  // [kRmseBlocks]
+    double *partial;  // [rmse_blocks(m)]
     double *out;      // one double
     Control *ctl;
     int p, n, m, s;

@@ -20,13 +20,13 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kWaveM = 32;  // rows of C per wave (2 MFMA tiles)
-constexpr int kWaveN = 32;  // cols of C per wave (2 MFMA tiles)
-constexpr int kBlockM = 64; // 2 x 2 waves per workgroup
-constexpr int kBlockN = 64;
+constexpr int kTM = 2;                // 16x16 MFMA tiles per wave along M
+constexpr int kTN = 4;                // 16x16 MFMA tiles per wave along N
+constexpr int kBlockM = 2 * 16 * kTM; // 2 x 2 waves per workgroup
+constexpr int kBlockN = 2 * 16 * kTN;
 
-__device__ inline void store_tile(float *C, int M, int N, int row0, int col0, const f32x4 &acc,
-                                  int lane)
+__device__ inline void store_tile(float *C, int M, int N, int ldc, int row0, int col0,
+                                  const f32x4 &acc, int lane)
 {
     const int col = col0 + (lane & 15);
     const int rbase = row0 + 4 * (lane >> 4);
@@ -36,124 +36,148 @@ __device__ inline void store_tile(float *C, int M, int N, int row0, int col0, co
     for (int r = 0; r < 4; ++r) {
         const int row = rbase + r;
         if (row < M)
-            C[(size_t)row * N + col] = acc[r];
+            C[(size_t)row * ldc + col] = acc[r];
     }
 }
 
-__global__ __launch_bounds__(256) void gemm_nt_f32_kernel(const float *__restrict__ A,
-                                                          const float *__restrict__ B,
-                                                          float *__restrict__ C, int M, int N,
-                                                          int K)
+// Which of the (up to two) problems of a grouped launch this workgroup
+// computes, and its tile origin.
+template <class P>
+__device__ inline bool pick_problem(const P &p0, const P &p1, int tiles_y0, P &out, int &row0,
+                                    int &col0)
 {
+    const int by = blockIdx.y;
+    out = by < tiles_y0 ? p0 : p1;
+    const int ty = by < tiles_y0 ? by : by - tiles_y0;
+    row0 = ty * kBlockM;
+    col0 = blockIdx.x * kBlockN;
+    return col0 < out.N && row0 < out.M;
+}
+
+__global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1, int tiles_y0)
+{
+    GemmF32 P;
+    int brow0, bcol0;
+    if (!pick_problem(p0, p1, tiles_y0, P, brow0, bcol0))
+        return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.y * kBlockM + (wave >> 1) * kWaveM;
-    const int col0 = blockIdx.x * kBlockN + (wave & 1) * kWaveN;
+    const int row0 = brow0 + (wave >> 1) * 16 * kTM;
+    const int col0 = bcol0 + (wave & 1) * 16 * kTN;
     const int r = lane & 15;
     const int kq = 4 * (lane >> 4);  // this lane's K offset inside a 16-wide K step
+    const int M = P.M, N = P.N, K = P.K;
 
-    f32x4 acc[2][2];
+    f32x4 acc[kTM][kTN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < kTM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < kTN; ++b)
             acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const int arow[2] = {row0 + r, row0 + 16 + r};
-    const int brow[2] = {col0 + r, col0 + 16 + r};
-
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const int k = k0 + kq;
-        f32x4 av[2], bv[2];
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        f32x4 av[2][kTM], bv[2][kTN];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            av[a] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (arow[a] < M && k < K)
-                av[a] = *reinterpret_cast<const f32x4 *>(A + (size_t)arow[a] * K + k);
-            bv[a] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (brow[a] < N && k < K)
-                bv[a] = *reinterpret_cast<const f32x4 *>(B + (size_t)brow[a] * K + k);
+        for (int h = 0; h < 2; ++h) {
+            const int k = k0 + 16 * h + kq;
+#pragma unroll
+            for (int a = 0; a < kTM; ++a) {
+                const int row = row0 + 16 * a + r;
+                av[h][a] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (row < M && k < K)
+                    av[h][a] = *reinterpret_cast<const f32x4 *>(P.A + (size_t)row * K + k);
+            }
+#pragma unroll
+            for (int b = 0; b < kTN; ++b) {
+                const int col = col0 + 16 * b + r;
+                bv[h][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (col < N && k < K)
+                    bv[h][b] = *reinterpret_cast<const f32x4 *>(P.B + (size_t)col * K + k);
+            }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][q], bv[b][q],
-                                                                      acc[a][b], 0, 0, 0);
+                for (int a = 0; a < kTM; ++a)
+#pragma unroll
+                    for (int b = 0; b < kTN; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h][a][q], bv[h][b][q],
+                                                                          acc[a][b], 0, 0, 0);
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < kTM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-            store_tile(C, M, N, row0 + 16 * a, col0 + 16 * b, acc[a][b], lane);
+        for (int b = 0; b < kTN; ++b)
+            store_tile(P.C, M, N, P.ldc, row0 + 16 * a, col0 + 16 * b, acc[a][b], lane);
 }
 
-__global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(const uint16_t *__restrict__ A,
-                                                           const uint16_t *__restrict__ B,
-                                                           float *__restrict__ C, int M, int N,
-                                                           int K)
+// 8 consecutive BF16 values (K % 4 == 0: a tail of 4 is loaded exactly).
+__device__ inline u16x8 load_bf16x8(const uint16_t *ptr, int k, int K)
 {
+    u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (k + 8 <= K) {
+        const uint2 lo = *reinterpret_cast<const uint2 *>(ptr);
+        const uint2 hi = *reinterpret_cast<const uint2 *>(ptr + 4);
+        v[0] = lo.x & 0xffff; v[1] = lo.x >> 16; v[2] = lo.y & 0xffff; v[3] = lo.y >> 16;
+        v[4] = hi.x & 0xffff; v[5] = hi.x >> 16; v[6] = hi.y & 0xffff; v[7] = hi.y >> 16;
+    } else if (k + 4 <= K) {
+        const uint2 lo = *reinterpret_cast<const uint2 *>(ptr);
+        v[0] = lo.x & 0xffff; v[1] = lo.x >> 16; v[2] = lo.y & 0xffff; v[3] = lo.y >> 16;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmBF16 p0, GemmBF16 p1, int tiles_y0)
+{
+    GemmBF16 P;
+    int brow0, bcol0;
+    if (!pick_problem(p0, p1, tiles_y0, P, brow0, bcol0))
+        return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.y * kBlockM + (wave >> 1) * kWaveM;
-    const int col0 = blockIdx.x * kBlockN + (wave & 1) * kWaveN;
+    const int row0 = brow0 + (wave >> 1) * 16 * kTM;
+    const int col0 = bcol0 + (wave & 1) * 16 * kTN;
     const int r = lane & 15;
     const int kq = 8 * (lane >> 4);  // 8 consecutive K values per lane in a 32-wide K step
+    const int M = P.M, N = P.N, K = P.K;
 
-    f32x4 acc[2][2];
+    f32x4 acc[kTM][kTN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < kTM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < kTN; ++b)
             acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const int arow[2] = {row0 + r, row0 + 16 + r};
-    const int brow[2] = {col0 + r, col0 + 16 + r};
 
     for (int k0 = 0; k0 < K; k0 += 32) {
         const int k = k0 + kq;
-        u16x8 av[2], bv[2];
+        u16x8 av[kTM], bv[kTN];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            // K % 4 == 0: load 8 values as two halves so a tail of 4 is exact
-            av[a] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-            bv[a] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-            if (arow[a] < M) {
-                const uint16_t *pa = A + (size_t)arow[a] * K + k;
-                if (k + 8 <= K) {
-                    av[a] = *reinterpret_cast<const u16x8 *>(pa);
-                } else if (k + 4 <= K) {
-                    const uint2 h = *reinterpret_cast<const uint2 *>(pa);
-                    av[a][0] = h.x & 0xffff; av[a][1] = h.x >> 16;
-                    av[a][2] = h.y & 0xffff; av[a][3] = h.y >> 16;
-                }
-            }
-            if (brow[a] < N) {
-                const uint16_t *pb = B + (size_t)brow[a] * K + k;
-                if (k + 8 <= K) {
-                    bv[a] = *reinterpret_cast<const u16x8 *>(pb);
-                } else if (k + 4 <= K) {
-                    const uint2 h = *reinterpret_cast<const uint2 *>(pb);
-                    bv[a][0] = h.x & 0xffff; bv[a][1] = h.x >> 16;
-                    bv[a][2] = h.y & 0xffff; bv[a][3] = h.y >> 16;
-                }
-            }
+        for (int a = 0; a < kTM; ++a) {
+            const int row = row0 + 16 * a + r;
+            av[a] = row < M ? load_bf16x8(P.A + (size_t)row * K + k, k, K)
+                            : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < kTN; ++b) {
+            const int col = col0 + 16 * b + r;
+            bv[b] = col < N ? load_bf16x8(P.B + (size_t)col * K + k, k, K)
+                            : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        }
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < kTM; ++a)
+#pragma unroll
+            for (int b = 0; b < kTN; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                     __builtin_bit_cast(bf16x8, av[a]), __builtin_bit_cast(bf16x8, bv[b]),
                     acc[a][b], 0, 0, 0);
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < kTM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-            store_tile(C, M, N, row0 + 16 * a, col0 + 16 * b, acc[a][b], lane);
+        for (int b = 0; b < kTN; ++b)
+            store_tile(P.C, M, N, P.ldc, row0 + 16 * a, col0 + 16 * b, acc[a][b], lane);
 }
 
 // Round-to-nearest-even FP32 -> BF16 on the bit pattern (NaN kept quiet).
@@ -174,22 +198,30 @@ __global__ void cast_bf16_kernel(const float *__restrict__ x, uint16_t *__restri
         y[k] = to_bf16_rne(x[k]);
 }
 
-}  // namespace
-
-hipError_t launch_gemm_nt_f32(const float *A, const float *B, float *C, int M, int N, int K,
-                              hipStream_t st)
+template <class P, class Kern>
+hipError_t launch_grouped(Kern kern, const P &p0, const P *p1, int kid, hipStream_t st)
 {
-    dim3 grid((N + kBlockN - 1) / kBlockN, (M + kBlockM - 1) / kBlockM);
-    hipLaunchKernelGGL(gemm_nt_f32_kernel, grid, dim3(256), 0, st, A, B, C, M, N, K);
+    const int ty0 = (p0.M + kBlockM - 1) / kBlockM;
+    const int ty1 = p1 ? (p1->M + kBlockM - 1) / kBlockM : 0;
+    int tx = (p0.N + kBlockN - 1) / kBlockN;
+    if (p1)
+        tx = tx > (p1->N + kBlockN - 1) / kBlockN ? tx : (p1->N + kBlockN - 1) / kBlockN;
+    prof_begin(kid, st);
+    hipLaunchKernelGGL(kern, dim3(tx, ty0 + ty1), dim3(256), 0, st, p0, p1 ? *p1 : p0, ty0);
+    prof_end(kid, st);
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_nt_bf16(const uint16_t *A, const uint16_t *B, float *C, int M, int N,
-                               int K, hipStream_t st)
+}  // namespace
+
+hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st)
 {
-    dim3 grid((N + kBlockN - 1) / kBlockN, (M + kBlockM - 1) / kBlockM);
-    hipLaunchKernelGGL(gemm_nt_bf16_kernel, grid, dim3(256), 0, st, A, B, C, M, N, K);
-    return hipGetLastError();
+    return launch_grouped(gemm_nt_f32_kernel, p0, p1, kid, st);
+}
+
+hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st)
+{
+    return launch_grouped(gemm_nt_bf16_kernel, p0, p1, kid, st);
 }
 
 hipError_t launch_cast_bf16(const float *x, uint16_t *y, size_t count, hipStream_t st)
@@ -199,7 +231,9 @@ hipError_t launch_cast_bf16(const float *x, uint16_t *y, size_t count, hipStream
     size_t blocks = (count + 255) / 256;
     if (blocks > 4096)
         blocks = 4096;
+    prof_begin(DL_K_MISC, st);
     hipLaunchKernelGGL(cast_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, y, count);
+    prof_end(DL_K_MISC, st);
     return hipGetLastError();
 }
 

@@ -56,9 +56,13 @@ __device__ inline int chunk_atom(const int32_t *chunk_ptr, int a0, int a1, int g
 }
 
 // ---- pass 1: partial F x^T per chunk ------------------------------------
+// The chunk's ELL positions and coefficients are staged in LDS first, so the
+// residual rows of several users are in flight at once.
 __global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1)
 {
     __shared__ f32x4 red[4][64];
+    __shared__ int sPos[kChunk];
+    __shared__ float sX[kChunk];
     const int p = a.p, s = a.s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpu = lanes_per_user(p);
@@ -71,15 +75,21 @@ __global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1
         const int gc = cbase + c;
         const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
         const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
-        const int u1 = min(u0 + kChunk, a.row_ptr[j + 1]);
+        const int cnt = min(kChunk, a.row_ptr[j + 1] - u0);
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+            const int pos = a.users[u0 + r];
+            sPos[r] = pos;
+            sX[r] = a.val[pos];
+        }
+        __syncthreads();
         const f32x4 d = load4(a.D + (size_t)j * p, q, p);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int stride = 4 * upw;
 #pragma unroll 4
-        for (int u = u0 + wave * upw + sub; u < u1; u += 4 * upw) {
-            const int pos = a.users[u];
-            const int i = pos / s;
-            const float x = a.val[pos];
-            const f32x4 e = load4(a.E + (size_t)i * p, q, p);
+        for (int r = wave * upw + sub; r < cnt; r += stride) {
+            const int pos = sPos[r];
+            const float x = sX[r];
+            const f32x4 e = load4(a.E + (size_t)(pos / s) * p, q, p);
             acc += (e + d * x) * x;
         }
         // sum over the user slots of the wave (lanes with the same q)
@@ -151,6 +161,8 @@ __global__ __launch_bounds__(256) void reduce_kernel(UpdateArgs a, int a0, int a
 // ---- pass 2: AK-SVD representation refresh ------------------------------
 __global__ __launch_bounds__(256) void pass2_kernel(UpdateArgs a, int a0, int a1)
 {
+    __shared__ int sPos[kChunk];
+    __shared__ float sX[kChunk];
     const int p = a.p, s = a.s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpu = lanes_per_user(p);
@@ -163,31 +175,42 @@ __global__ __launch_bounds__(256) void pass2_kernel(UpdateArgs a, int a0, int a1
         const int gc = cbase + c;
         const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
         const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
-        const int u1 = min(u0 + kChunk, a.row_ptr[j + 1]);
+        const int cnt = min(kChunk, a.row_ptr[j + 1] - u0);
         const bool keep = a.rule != DL_RULE_AKSVD || a.atom_state[j] != 0;
-        const f32x4 d = load4(a.D + (size_t)j * p, q, p);
-        const f32x4 dn = load4(a.Dn + (size_t)j * p, q, p);
-        // every lane of the wave runs the same trip count (shuffles below)
-        for (int ub = u0 + wave * upw; ub < u1; ub += 4 * upw) {
-            const int u = ub + sub;
-            const bool on = u < u1;
-            float part = 0.f;
-            int pos = 0;
-            float x = 0.f;
-            if (on) {
-                pos = a.users[u];
-                x = a.val[pos];
-                if (!keep) {
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+            const int pos = a.users[u0 + r];
+            sPos[r] = pos;
+            sX[r] = a.val[pos];
+        }
+        __syncthreads();
+        if (keep) {
+            for (int r = threadIdx.x; r < cnt; r += blockDim.x)
+                a.valn[sPos[r]] = sX[r];
+        } else {
+            const f32x4 d = load4(a.D + (size_t)j * p, q, p);
+            const f32x4 dn = load4(a.Dn + (size_t)j * p, q, p);
+            const int stride = 4 * upw;
+            // every lane of the wave runs the same trip count (shuffles below)
+#pragma unroll 2
+            for (int rb = wave * upw; rb < cnt; rb += stride) {
+                const int r = rb + sub;
+                const bool on = r < cnt;
+                float part = 0.f;
+                int pos = 0;
+                if (on) {
+                    pos = sPos[r];
+                    const float x = sX[r];
                     const f32x4 e = load4(a.E + (size_t)(pos / s) * p, q, p);
                     const f32x4 f = e + d * x;
                     part = f[0] * dn[0] + f[1] * dn[1] + f[2] * dn[2] + f[3] * dn[3];
                 }
+                for (int off = 1; off < lpu; off <<= 1)
+                    part += __shfl_xor(part, off);
+                if (on && (lane % lpu) == 0)
+                    a.valn[pos] = part;
             }
-            for (int off = 1; off < lpu; off <<= 1)
-                part += __shfl_xor(part, off);
-            if (on && (lane % lpu) == 0)
-                a.valn[pos] = keep ? x : part;
         }
+        __syncthreads();
     }
 }
 
@@ -238,33 +261,44 @@ __global__ __launch_bounds__(256) void eupdate_kernel(UpdateArgs a, int a0, int 
 }
 
 // ---- error ||Y - D X||_F^2 with an FP64 reduction ------------------------
+// One workgroup per block of kRmseSignals signals: the block's X rows are
+// staged in LDS, each lane group forms one residual row at a time, squares
+// are accumulated in FP64; the last workgroup to finish sums the per-block
+// partials in block order.
 __global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
 {
     __shared__ double red[256];
+    __shared__ int sIdx[kRmseSignals * 16];
+    __shared__ float sVal[kRmseSignals * 16];
     __shared__ bool am_last;
-    const int p = a.p, s = a.s;
-    const int lane = threadIdx.x & 63;
+    const int p = a.p, s = a.s, n = a.n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpu = lanes_per_user(p);
     const int upw = 64 / lpu;
     const int sub = lane / lpu;
     const int q = 4 * (lane % lpu);
-    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int nw = gridDim.x * 4;
+    const int i0 = blockIdx.x * kRmseSignals;
+    const int nsig = min(kRmseSignals, a.m - i0);
+    for (int r = threadIdx.x; r < nsig * s; r += blockDim.x) {
+        sIdx[r] = a.idx[(size_t)i0 * s + r];
+        sVal[r] = a.val[(size_t)i0 * s + r];
+    }
+    __syncthreads();
     double acc = 0.0;
-    for (int i = wid * upw + sub; i < a.m; i += nw * upw) {
-        if (q >= p)
-            continue;
-        f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
-        for (int t = 0; t < s; ++t) {
-            const int j = a.idx[(size_t)i * s + t];
-            if (j < 0 || j >= a.n)
-                continue;
-            const float x = a.val[(size_t)i * s + t];
-            e -= *reinterpret_cast<const f32x4 *>(a.D + (size_t)j * p + q) * x;
-        }
+    if (q < p) {
+        for (int il = wave * upw + sub; il < nsig; il += 4 * upw) {
+            const int i = i0 + il;
+            f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
+            for (int t = 0; t < s; ++t) {
+                const int j = sIdx[il * s + t];
+                if (j < 0 || j >= n)
+                    continue;
+                e -= *reinterpret_cast<const f32x4 *>(a.D + (size_t)j * p + q) * sVal[il * s + t];
+            }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            acc += (double)e[r] * (double)e[r];
+            for (int r = 0; r < 4; ++r)
+                acc += (double)e[r] * (double)e[r];
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -389,6 +423,8 @@ unsigned grid_for(size_t items, unsigned cap)
 
 }  // namespace
 
+int rmse_blocks(int m) { return (m + kRmseSignals - 1) / kRmseSignals; }
+
 int max_chunks(const dl_params &prm)
 {
     const long long ms = (long long)prm.m * prm.s;
@@ -408,19 +444,27 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
         if (chunks_ub > a.max_chunks)
             chunks_ub = a.max_chunks;
         const unsigned grid = (unsigned)(chunks_ub > 2048 ? 2048 : (chunks_ub < 1 ? 1 : chunks_ub));
+        prof_begin(DL_K_UPD_PASS1, st);
         hipLaunchKernelGGL(pass1_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
+        prof_end(DL_K_UPD_PASS1, st);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
+        prof_begin(DL_K_UPD_REDUCE, st);
         hipLaunchKernelGGL(reduce_kernel, dim3((a1 - a0 + 3) / 4), dim3(256), 0, st, a, a0, a1);
+        prof_end(DL_K_UPD_REDUCE, st);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
+        prof_begin(DL_K_UPD_PASS2, st);
         hipLaunchKernelGGL(pass2_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
+        prof_end(DL_K_UPD_PASS2, st);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (a1 < a.n) {
             const unsigned eg = grid_for((size_t)users_ub * 16, 2048);
+            prof_begin(DL_K_UPD_EUPDATE, st);
             hipLaunchKernelGGL(eupdate_kernel, dim3(eg), dim3(256), 0, st, a, a0, a1);
+            prof_end(DL_K_UPD_EUPDATE, st);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
         }
@@ -430,21 +474,27 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
 
 hipError_t launch_rmse(const RmseArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(rmse_kernel, dim3(kRmseBlocks), dim3(256), 0, st, a);
+    prof_begin(DL_K_RMSE, st);
+    hipLaunchKernelGGL(rmse_kernel, dim3(rmse_blocks(a.m)), dim3(256), 0, st, a);
+    prof_end(DL_K_RMSE, st);
     return hipGetLastError();
 }
 
 hipError_t launch_residual(const float *Y, const float *D, const int32_t *idx, const float *val,
                            float *E, int p, int n, int m, int s, hipStream_t st)
 {
+    prof_begin(DL_K_MISC, st);
     hipLaunchKernelGGL(residual_kernel, dim3(grid_for((size_t)m * 16, 4096)), dim3(256), 0, st, Y,
                        D, idx, val, E, p, n, m, s);
+    prof_end(DL_K_MISC, st);
     return hipGetLastError();
 }
 
 hipError_t launch_normalize_rows(float *D, int n, int p, Control *ctl, hipStream_t st)
 {
+    prof_begin(DL_K_MISC, st);
     hipLaunchKernelGGL(normalize_kernel, dim3((n + 3) / 4), dim3(256), 0, st, D, n, p, ctl);
+    prof_end(DL_K_MISC, st);
     return hipGetLastError();
 }
 
@@ -453,8 +503,10 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
     const size_t words = bytes / 4;  // every buffer here is a multiple of 4 bytes
     if (words == 0)
         return hipSuccess;
+    prof_begin(DL_K_MISC, st);
     hipLaunchKernelGGL(copy_kernel, dim3(grid_for(words, 4096)), dim3(256), 0, st,
                        (const uint32_t *)src, (uint32_t *)dst, words);
+    prof_end(DL_K_MISC, st);
     return hipGetLastError();
 }
 
@@ -463,8 +515,10 @@ hipError_t launch_zero(void *dst, size_t bytes, hipStream_t st)
     const size_t words = bytes / 4;
     if (words == 0)
         return hipSuccess;
+    prof_begin(DL_K_MISC, st);
     hipLaunchKernelGGL(zero_kernel, dim3(grid_for(words, 4096)), dim3(256), 0, st,
                        (uint32_t *)dst, words);
+    prof_end(DL_K_MISC, st);
     return hipGetLastError();
 }
 

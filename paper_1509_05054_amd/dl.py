@@ -35,7 +35,8 @@ class _Params(ctypes.Structure):
         ("p", ctypes.c_int), ("n", ctypes.c_int), ("m", ctypes.c_int), ("s", ctypes.c_int),
         ("group_size", ctypes.c_int), ("precision", ctypes.c_int), ("rule", ctypes.c_int),
         ("pivot_fp64_threshold", ctypes.c_float), ("tol_corr", ctypes.c_float),
-        ("tol_pivot", ctypes.c_float),
+        ("tol_pivot", ctypes.c_float), ("omp_lanes_per_signal", ctypes.c_int),
+        ("omp_atoms_per_lane", ctypes.c_int),
     ]
 
 
@@ -70,7 +71,14 @@ SIGNATURES = {
     "dl_iterate": (ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp]),
     "dl_read_stats": (ctypes.c_int, [_PP, _vp, ctypes.c_size_t, ctypes.POINTER(Stats), _vp]),
+    "dl_profile_enable": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "dl_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
 }
+
+# kernel ids of dl_profile_read (enum dl_kernel)
+KERNELS = ["gram", "corr", "omp", "csr_count", "csr_scan", "csr_scatter", "upd_pass1",
+           "upd_reduce", "upd_pass2", "upd_eupdate", "rmse", "misc"]
 
 
 def lib():
@@ -113,12 +121,14 @@ class Params:
     pivot_fp64_threshold: float = 1e-6
     tol_corr: float = 1e-5
     tol_pivot: float = 1e-10
+    omp_lanes_per_signal: int = 0
+    omp_atoms_per_lane: int = 0
 
     def c(self) -> _Params:
         return _Params(self.p, self.n, self.m, self.s,
                        self.n if self.group_size is None else self.group_size,
                        self.precision, self.rule, self.pivot_fp64_threshold, self.tol_corr,
-                       self.tol_pivot)
+                       self.tol_pivot, self.omp_lanes_per_signal, self.omp_atoms_per_lane)
 
     def ref(self):
         self._c = self.c()  # keep alive for the call
@@ -184,6 +194,20 @@ def rmse(prm: Params, Y, D, X_idx, X_val, out, ws, stream=None):
 def iterate(prm: Params, Y, D, iters, X_idx, X_val, rmse_out, ws, stream=None):
     _check(lib().dl_iterate(prm.ref(), _ptr(Y), _ptr(D), int(iters), _ptr(X_idx), _ptr(X_val),
                             _ptr(rmse_out), _ptr(ws), ws.numel(), _stream(stream)), "dl_iterate")
+
+
+def profile_enable(on: bool, max_launches: int = 1 << 16):
+    """Per-kernel HIP-event timing inside the library (measurement only)."""
+    _check(lib().dl_profile_enable(int(bool(on)), int(max_launches)), "dl_profile_enable")
+
+
+def profile_read() -> dict:
+    """{kernel: (total_ms, launches)} since the last read; waits for the events."""
+    k = len(KERNELS)
+    ms = (ctypes.c_double * k)()
+    cnt = (ctypes.c_longlong * k)()
+    _check(lib().dl_profile_read(ms, cnt, k), "dl_profile_read")
+    return {KERNELS[i]: (float(ms[i]), int(cnt[i])) for i in range(k)}
 
 
 def read_stats(prm: Params, ws, stream=None, allow_nonfinite=False) -> dict:

@@ -162,7 +162,10 @@ def test_omp_fp64_pivot_path():
     assert st["fp64_pivot_recomputes"] >= 4, st
     np.testing.assert_array_equal(ig, ir)
     assert all(list(row) == [1, 0] for row in ig)
-    np.testing.assert_allclose(vg, vr, rtol=2e-2)
+    # The pivot is recomputed in FP64 from the FP32 entries of G: G_AB rounded
+    # to FP32 (spacing 6e-8 near 1) moves 1 - G_AB^2 ~ 2.4e-7 by about 5%, and
+    # the coefficients, which scale with 1/delta, move with it.
+    np.testing.assert_allclose(vg, vr, rtol=0.1)
 
 
 # ---------------------------------------------------------------- CSR
@@ -312,3 +315,16 @@ def test_iterate_is_deterministic_and_resumable():
     Db, ib, vb, rb, _ = _gpu_iterate(w, 2, 256, D0=Da)
     np.testing.assert_array_equal(Db, D1)
     np.testing.assert_array_equal(np.concatenate([ra, rb]), r1)
+
+
+@pytest.mark.parametrize("lps,npl", [(16, 16), (32, 8), (64, 8), (64, 16), (32, 16)])
+def test_omp_launch_shapes_agree(lps, npl):
+    """Every launch shape of the OMP kernel computes the same supports and
+    coefficients (only the summation order of ||y|| differs)."""
+    note(f"omp launch shape lps={lps} npl={npl}")
+    Y, D = _patch_problem(64, 256, 3001, seed=77)
+    i0, v0, _ = gpu_omp(D, Y, 6)
+    i1, v1, _ = gpu_omp(D, Y, 6, omp_lanes_per_signal=lps, omp_atoms_per_lane=npl)
+    assert np.mean(np.all(i0 == i1, axis=1)) >= 0.999
+    same = np.all(i0 == i1, axis=1)
+    np.testing.assert_array_equal(v0[same], v1[same])
