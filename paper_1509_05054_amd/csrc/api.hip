@@ -80,8 +80,8 @@ bool valid_params(const dl_params *prm)
     if (q.omp_lanes_per_signal != 0 || q.omp_atoms_per_lane != 0) {
         const int npl = q.omp_atoms_per_lane ? q.omp_atoms_per_lane : 16;
         const int lps = q.omp_lanes_per_signal ? q.omp_lanes_per_signal
-                                               : omp_lanes_per_signal(q.n, npl);
-        if (!omp_config_ok(q.n, lps, npl))
+                                               : omp_lanes_per_signal(q.n, npl, q.s);
+        if (!omp_config_ok(q.n, q.s, lps, npl))
             return false;
     }
     return true;

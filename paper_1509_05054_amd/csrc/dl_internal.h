@@ -96,8 +96,8 @@ struct OmpArgs {
     float pivot_fp64, tol_corr, tol_pivot;
 };
 hipError_t launch_omp(const OmpArgs &a, hipStream_t st);
-int omp_lanes_per_signal(int n, int npl);
-bool omp_config_ok(int n, int lps, int npl);
+int omp_lanes_per_signal(int n, int npl, int s);
+bool omp_config_ok(int n, int s, int lps, int npl);
 // Leading dimension used for G and A0 rows.
 inline int padded_n(int n) { return (n + 3) & ~3; }
 

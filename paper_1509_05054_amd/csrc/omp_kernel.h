@@ -1,0 +1,412 @@
+// Sparse coding (step 1 of the DL iteration, Alg. 1): OMP with fixed
+// sparsity s, computed Batch-OMP style from G = D D^T and A0 = Y D^T.
+// Included by the omp_npl*.hip translation units, which instantiate it.
+//
+// A signal is handled by a group of LPS lanes of a wavefront (64/LPS signals
+// per wave); lane l of the group owns atoms [l*NPL, (l+1)*NPL) and row l of
+// the Cholesky factor L of G_II.  The group keeps the correlations
+// alpha = D^T r of the signal's current residual in registers.  Step k:
+//   1. j = argmax over unselected atoms of |alpha_j| (ties: lowest index),
+//      reduced over the group with DPP moves;
+//   2. the new row of L: w = L^{-1} G[I, j] by forward substitution (lane t
+//      loads G[j][I_t]; each round broadcasts one w_t inside the group), and
+//      delta^2 = G_jj - |w|^2; pivots below `pivot_fp64` are recomputed in
+//      FP64;
+//   3. c_k = (A0_j - sum_t w_t c_t) / delta, the coefficient of y on the
+//      orthonormalised new direction q_k;
+//   4. u_k = (G[j,:] - sum_t w_t u_t) / delta (= D^T q_k) and
+//      alpha -= c_k u_k, so that alpha stays the correlation of the residual
+//      (not needed after the last step).
+// The coefficients then solve L^T x = c (D_I = Q L^T), by back substitution
+// with group sums.  This is the arithmetic of Batch-OMP (alpha = A0 - G_I
+// gamma with gamma = G_II^{-1} A0_I), reorganised so that a step is one pass
+// over the n correlations plus k short rounds.
+//
+// G and A0 rows have leading dimension ldn (a multiple of 4: rows load as
+// float4).  Requirements: LPS in {4..64}, LPS >= SMAX >= s, LPS*NPL >= n.
+#pragma once
+
+#include "dl_internal.h"
+
+namespace dlk {
+namespace omp_detail {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;  // waves per workgroup
+
+__device__ inline float bits_f(int v) { return __int_as_float(v); }
+__device__ inline int f_bits(float v) { return __float_as_int(v); }
+
+// Order this wave's LDS stores before its later LDS loads from other lanes.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ inline int dpp(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+// Combine (value, index) pairs: larger value wins, lower index on ties.
+__device__ inline void take_better(float &v, int &ix, float ov, int oi)
+{
+    if (ov > v || (ov == v && oi < ix)) {
+        v = ov;
+        ix = oi;
+    }
+}
+
+// All-reduce of (max value, lowest index) over groups of LPS lanes.
+template <int LPS>
+__device__ inline void group_argmax(float &v, int &ix)
+{
+    if constexpr (LPS >= 2)
+        take_better(v, ix, bits_f(dpp<0xB1>(f_bits(v))), dpp<0xB1>(ix));      // lane ^ 1
+    if constexpr (LPS >= 4)
+        take_better(v, ix, bits_f(dpp<0x4E>(f_bits(v))), dpp<0x4E>(ix));      // lane ^ 2
+    if constexpr (LPS >= 8)
+        take_better(v, ix, bits_f(dpp<0x141>(f_bits(v))), dpp<0x141>(ix));    // half-row mirror
+    if constexpr (LPS >= 16)
+        take_better(v, ix, bits_f(dpp<0x140>(f_bits(v))), dpp<0x140>(ix));    // row mirror
+    if constexpr (LPS >= 32)
+        take_better(v, ix, __shfl_xor(v, 16), __shfl_xor(ix, 16));
+    if constexpr (LPS >= 64)
+        take_better(v, ix, __shfl_xor(v, 32), __shfl_xor(ix, 32));
+}
+
+template <int LPS>
+__device__ inline float group_sum(float v)
+{
+    if constexpr (LPS >= 2)
+        v += bits_f(dpp<0xB1>(f_bits(v)));
+    if constexpr (LPS >= 4)
+        v += bits_f(dpp<0x4E>(f_bits(v)));
+    if constexpr (LPS >= 8)
+        v += bits_f(dpp<0x141>(f_bits(v)));
+    if constexpr (LPS >= 16)
+        v += bits_f(dpp<0x140>(f_bits(v)));
+    if constexpr (LPS >= 32)
+        v += __shfl_xor(v, 16);
+    if constexpr (LPS >= 64)
+        v += __shfl_xor(v, 32);
+    return v;
+}
+
+// Value of lane R of each group, in every lane of that group.
+template <int LPS, int R>
+__device__ inline float group_bcast(float v)
+{
+    if constexpr (LPS == 64) {
+        return bits_f(__builtin_amdgcn_readlane(f_bits(v), R));
+    } else {
+        // ds_swizzle bit mode inside 32 lanes: source = (lane & and) | or
+        constexpr int and_mask = 31 & ~(LPS - 1);
+        constexpr int pattern = and_mask | (R << 5);
+        return bits_f(__builtin_amdgcn_ds_swizzle(f_bits(v), pattern));
+    }
+}
+
+template <int NPL>
+using vec_t = float __attribute__((ext_vector_type(NPL)));
+
+template <int NPL>
+__device__ inline void load_row(vec_t<NPL> &v, const float *row, int first, int ldn, bool on)
+{
+#pragma unroll
+    for (int c4 = 0; c4 < NPL / 4; ++c4) {
+        const int at = first + 4 * c4;
+        f32x4 x = {0.f, 0.f, 0.f, 0.f};
+        if (on && at < ldn)
+            x = *reinterpret_cast<const f32x4 *>(row + at);
+        v[4 * c4 + 0] = x[0];
+        v[4 * c4 + 1] = x[1];
+        v[4 * c4 + 2] = x[2];
+        v[4 * c4 + 3] = x[3];
+    }
+}
+
+template <int LPS, int NPL, int SMAX>
+__global__ __launch_bounds__(64 * kWaves) void omp_kernel(OmpArgs a)
+{
+    static_assert(LPS >= SMAX, "one lane per row of L");
+    constexpr int GPW = 64 / LPS;                 // signals per wave
+    constexpr int US = SMAX > 1 ? SMAX - 1 : 1;   // stored u vectors
+    // rare FP64 pivot path only
+    __shared__ float sL[kWaves][GPW][SMAX * SMAX];
+    __shared__ float sB[kWaves][GPW][SMAX];
+    __shared__ double sW[kWaves][GPW][SMAX];
+    __shared__ double sD2[kWaves][GPW];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int grp = lane / LPS;   // signal slot of this lane in the wave
+    const int l = lane % LPS;     // lane within the group
+    const int wave_sig0 = (blockIdx.x * kWaves + wave) * GPW;
+    if (wave_sig0 >= a.m)
+        return;  // whole wave leaves together; no workgroup barrier follows
+    const int i = wave_sig0 + grp;
+    const bool valid = i < a.m;
+    const int n = a.n, p = a.p, s = a.s, ldn = a.ldn;
+
+    // ||y|| for the orthogonality stop rule
+    float ysq = 0.f;
+    if (valid)
+        for (int q = 4 * l; q < p; q += 4 * LPS) {
+            const f32x4 y = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
+            ysq += y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3];
+        }
+    const float ynorm = sqrtf(group_sum<LPS>(ysq));
+    const float thr = a.tol_corr * ynorm;
+
+    // correlations of y; atoms beyond n are marked as taken
+    const int a_first = l * NPL;
+    vec_t<NPL> alpha;
+    load_row<NPL>(alpha, a.A0 + (size_t)i * ldn, a_first, ldn, valid);
+    unsigned taken = 0;
+#pragma unroll
+    for (int c = 0; c < NPL; ++c)
+        if (a_first + c >= n)
+            taken |= 1u << c;
+
+    vec_t<NPL> u[US];
+    float Lrow[SMAX];     // row l of L (this lane's row)
+    float cv[SMAX];       // c_t, the same in every lane of the group
+    float dg[SMAX];       // L[t][t]
+    int js[SMAX];         // selected atoms
+    int selj = -1;        // this lane's atom (row l)
+#pragma unroll
+    for (int t = 0; t < SMAX; ++t) {
+        Lrow[t] = 0.f;
+        cv[t] = 0.f;
+        dg[t] = 1.f;
+        js[t] = 0;
+    }
+    bool active = valid && isfinite(ynorm);
+    if (valid && !isfinite(ynorm) && l == 0)
+        atomicAdd(&a.ctl->nonfinite, 1ull);
+    int kg = 0;  // atoms selected for this lane's signal
+
+#pragma unroll 1
+    for (int k = 0; k < s; ++k) {
+        if (!__any(active))
+            break;
+        // 1. masked argmax over the group, lowest index on ties
+        float best = -1.f;
+        int bidx = 0x7fffffff;
+#pragma unroll
+        for (int c = 0; c < NPL; ++c) {
+            const float v = fabsf(alpha[c]);
+            if (!((taken >> c) & 1u) && v > best) {
+                best = v;
+                bidx = a_first + c;
+            }
+        }
+        group_argmax<LPS>(best, bidx);
+        bool ok = active && best > thr && bidx < n;
+        const int j = ok ? bidx : 0;
+        const float *Gj = a.G + (size_t)j * ldn;
+
+        // 2. loads for this step: the G row, G_jj, A0_j, and G[j][I_l]
+        vec_t<NPL> g;
+        load_row<NPL>(g, Gj, a_first, ldn, ok);
+        const float gjj = ok ? Gj[j] : 1.f;
+        const float a0j = ok ? a.A0[(size_t)i * ldn + j] : 0.f;
+        float acc = (ok && l < k) ? Gj[selj] : 0.f;
+
+        // forward substitution L w = G[I, j]: round t finalises w_t in lane t
+        float w[US];
+        float d2 = gjj;
+#pragma unroll
+        for (int t = 0; t < US; ++t) {
+            w[t] = 0.f;
+            if (t < k) {
+                float wt = acc / Lrow[t];     // meaningful in lane t
+                switch (t) {                  // broadcast lane t of the group
+#define DL_BCAST_CASE(T) \
+    case T:              \
+        if constexpr (T < LPS) wt = group_bcast<LPS, T>(wt); \
+        break;
+                    DL_BCAST_CASE(0) DL_BCAST_CASE(1) DL_BCAST_CASE(2) DL_BCAST_CASE(3)
+                    DL_BCAST_CASE(4) DL_BCAST_CASE(5) DL_BCAST_CASE(6) DL_BCAST_CASE(7)
+                    DL_BCAST_CASE(8) DL_BCAST_CASE(9) DL_BCAST_CASE(10) DL_BCAST_CASE(11)
+                    DL_BCAST_CASE(12) DL_BCAST_CASE(13) DL_BCAST_CASE(14)
+#undef DL_BCAST_CASE
+                default: break;
+                }
+                w[t] = wt;
+                if (l > t)
+                    acc -= Lrow[t] * wt;
+                d2 -= wt * wt;
+            }
+        }
+        const bool need64 = ok && d2 < a.pivot_fp64;
+        if (__any(need64)) {
+            // rare: w and the pivot again in FP64 (the group's first lane
+            // substitutes serially from L and G[I, j] staged in LDS)
+            if (need64 && l < k) {
+#pragma unroll
+                for (int r = 0; r < SMAX; ++r)
+                    if (r <= l)
+                        sL[wave][grp][l * SMAX + r] = Lrow[r];
+                sB[wave][grp][l] = Gj[selj];
+            }
+            wave_lds_sync();
+            if (need64 && l == 0) {
+                double d2_64 = (double)gjj;
+                for (int t = 0; t < k; ++t) {
+                    double accd = (double)sB[wave][grp][t];
+                    for (int r = 0; r < t; ++r)
+                        accd -= (double)sL[wave][grp][t * SMAX + r] * sW[wave][grp][r];
+                    sW[wave][grp][t] = accd / (double)sL[wave][grp][t * SMAX + t];
+                    d2_64 -= sW[wave][grp][t] * sW[wave][grp][t];
+                }
+                sD2[wave][grp] = d2_64;
+                atomicAdd(&a.ctl->fp64_pivot_recomputes, 1ull);
+            }
+            wave_lds_sync();
+            if (need64) {
+                const double d2_64 = sD2[wave][grp];
+                if (!(d2_64 > (double)a.tol_pivot * (double)gjj)) {
+                    ok = false;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < US; ++t)
+                        if (t < k)
+                            w[t] = (float)sW[wave][grp][t];
+                    d2 = (float)d2_64;
+                }
+            }
+            wave_lds_sync();
+        }
+        if (!ok)
+            active = false;
+        const float delta = sqrtf(d2);
+        const float inv = 1.0f / delta;
+
+        // 3. coefficient of y on q_k
+        float ck = a0j;
+#pragma unroll
+        for (int t = 0; t < US; ++t)
+            if (t < k)
+                ck -= w[t] * cv[t];
+        ck *= inv;
+
+        // 4. u_k and the correlation update (not needed after the last step)
+        if (ok && k + 1 < s) {
+            vec_t<NPL> unew = g;
+#pragma unroll
+            for (int t = 0; t < US; ++t)
+                if (t < k)
+                    unew -= w[t] * u[t];
+            unew *= inv;
+            alpha -= ck * unew;
+#pragma unroll
+            for (int t = 0; t < US; ++t)
+                if (t == k)
+                    u[t] = unew;
+        }
+        if (ok) {
+            if (l == j / NPL)
+                taken |= 1u << (j % NPL);
+#pragma unroll
+            for (int t = 0; t < SMAX; ++t)
+                if (t == k) {
+                    cv[t] = ck;
+                    dg[t] = delta;
+                    js[t] = j;
+                }
+            if (l == k) {
+#pragma unroll
+                for (int t = 0; t < US; ++t)
+                    if (t < k)
+                        Lrow[t] = w[t];
+#pragma unroll
+                for (int t = 0; t < SMAX; ++t)
+                    if (t == k)
+                        Lrow[t] = delta;
+                selj = j;
+            }
+            kg = k + 1;
+        }
+    }
+    if (valid && l == 0 && kg < s)
+        atomicAdd(&a.ctl->early_stops, 1ull);
+
+    // coefficients: L^T x = c, from the last row up; lane t holds L[t][*]
+    float xs[SMAX];
+    float xown = 0.f;
+#pragma unroll
+    for (int r = SMAX - 1; r >= 0; --r) {
+        const float part = (l > r && l < kg) ? Lrow[r] * xown : 0.f;
+        const float ssum = group_sum<LPS>(part);
+        const float xr = (cv[r] - ssum) / dg[r];
+        xs[r] = r < kg ? xr : 0.f;
+        if (l == r)
+            xown = xs[r];
+    }
+    if (!valid)
+        return;
+    if (l < s) {
+        const bool on = l < kg;
+        a.idx[(size_t)i * s + l] = on ? selj : -1;
+        a.val[(size_t)i * s + l] = on ? xown : 0.f;
+    }
+    // residual e = y - D_I x with the dictionary used for coding
+    if (a.E) {
+        for (int q = 4 * l; q < p; q += 4 * LPS) {
+            f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
+#pragma unroll
+            for (int t = 0; t < SMAX; ++t)
+                if (t < kg) {
+                    const f32x4 d = *reinterpret_cast<const f32x4 *>(a.D + (size_t)js[t] * p + q);
+                    e -= d * xs[t];
+                }
+            *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e;
+        }
+    }
+}
+
+template <int LPS, int NPL, int SMAX>
+hipError_t launch_omp_t(const OmpArgs &a, hipStream_t st)
+{
+    constexpr int sig_per_block = kWaves * (64 / LPS);
+    const int blocks = (a.m + sig_per_block - 1) / sig_per_block;
+    prof_begin(DL_K_OMP, st);
+    hipLaunchKernelGGL((omp_kernel<LPS, NPL, SMAX>), dim3(blocks), dim3(64 * kWaves), 0, st, a);
+    prof_end(DL_K_OMP, st);
+    return hipGetLastError();
+}
+
+// Dispatch over SMAX for one (LPS, NPL); configurations with LPS < SMAX are
+// never requested (omp_config_ok rejects them).
+template <int LPS, int NPL>
+hipError_t launch_omp_s(const OmpArgs &a, hipStream_t st)
+{
+    if (a.s <= 4)
+        return launch_omp_t<LPS, NPL, 4>(a, st);
+    if constexpr (LPS >= 8) {
+        if (a.s <= 6)
+            return launch_omp_t<LPS, NPL, 6>(a, st);
+        if (a.s <= 8)
+            return launch_omp_t<LPS, NPL, 8>(a, st);
+    }
+    if constexpr (LPS >= 16) {
+        if (a.s <= 12)
+            return launch_omp_t<LPS, NPL, 12>(a, st);
+        return launch_omp_t<LPS, NPL, 16>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace omp_detail
+
+hipError_t launch_omp_npl4(const OmpArgs &a, int lps, hipStream_t st);
+hipError_t launch_omp_npl8(const OmpArgs &a, int lps, hipStream_t st);
+hipError_t launch_omp_npl16(const OmpArgs &a, int lps, hipStream_t st);
+
+}  // namespace dlk

@@ -1,0 +1,19 @@
+// Instantiations of the OMP kernel with 16 correlations per lane.
+#include "omp_kernel.h"
+
+namespace dlk {
+
+hipError_t launch_omp_npl16(const OmpArgs &a, int lps, hipStream_t st)
+{
+    using namespace omp_detail;
+    switch (lps) {
+    case 4: return launch_omp_s<4, 16>(a, st);
+    case 8: return launch_omp_s<8, 16>(a, st);
+    case 16: return launch_omp_s<16, 16>(a, st);
+    case 32: return launch_omp_s<32, 16>(a, st);
+    case 64: return launch_omp_s<64, 16>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dlk

@@ -1,0 +1,19 @@
+// Instantiations of the OMP kernel with 4 correlations per lane.
+#include "omp_kernel.h"
+
+namespace dlk {
+
+hipError_t launch_omp_npl4(const OmpArgs &a, int lps, hipStream_t st)
+{
+    using namespace omp_detail;
+    switch (lps) {
+    case 4: return launch_omp_s<4, 4>(a, st);
+    case 8: return launch_omp_s<8, 4>(a, st);
+    case 16: return launch_omp_s<16, 4>(a, st);
+    case 32: return launch_omp_s<32, 4>(a, st);
+    case 64: return launch_omp_s<64, 4>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dlk

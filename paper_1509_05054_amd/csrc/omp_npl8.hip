@@ -1,0 +1,19 @@
+// Instantiations of the OMP kernel with 8 correlations per lane.
+#include "omp_kernel.h"
+
+namespace dlk {
+
+hipError_t launch_omp_npl8(const OmpArgs &a, int lps, hipStream_t st)
+{
+    using namespace omp_detail;
+    switch (lps) {
+    case 4: return launch_omp_s<4, 8>(a, st);
+    case 8: return launch_omp_s<8, 8>(a, st);
+    case 16: return launch_omp_s<16, 8>(a, st);
+    case 32: return launch_omp_s<32, 8>(a, st);
+    case 64: return launch_omp_s<64, 8>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dlk

@@ -317,7 +317,7 @@ def test_iterate_is_deterministic_and_resumable():
     np.testing.assert_array_equal(np.concatenate([ra, rb]), r1)
 
 
-@pytest.mark.parametrize("lps,npl", [(16, 16), (32, 8), (64, 8), (64, 16), (32, 16)])
+@pytest.mark.parametrize("lps,npl", [(16, 16), (32, 8), (64, 4), (64, 16), (32, 16)])
 def test_omp_launch_shapes_agree(lps, npl):
     """Every launch shape of the OMP kernel computes the same supports and
     coefficients (only the summation order of ||y|| differs)."""
