@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096, help="signals in the CPU sample")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
+                    help="products' precision (default: the workload's own)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -117,7 +119,9 @@ def main():
     w = synth.workload(args.workload)
     iters = args.iters or w.iters
     gs = args.group_size or w.n
-    prm = dl.Params(w.p, w.n, w.m, w.s, group_size=gs)
+    precision = args.precision or ("bf16" if args.workload.startswith("patches_p256") else "fp32")
+    prm = dl.Params(w.p, w.n, w.m, w.s, group_size=gs,
+                    precision=dl.PREC_BF16 if precision == "bf16" else dl.PREC_FP32)
     dev = torch.device("cuda:0")
     Y = torch.from_numpy(w.Y).to(dev)
     D0 = torch.from_numpy(w.D0).to(dev)
@@ -166,7 +170,8 @@ def main():
     if bound == "hbm":
         achieved, peak, runit = amount / avg_s / 1e9, PEAK_HBM / 1e9, "GB/s"
     elif bound == "mfma":
-        achieved, peak, runit = amount / avg_s / 1e12, PEAK_FP32_MFMA / 1e12, "TFLOP/s"
+        mfma_peak = PEAK_BF16_MFMA if precision == "bf16" else PEAK_FP32_MFMA
+        achieved, peak, runit = amount / avg_s / 1e12, mfma_peak / 1e12, "TFLOP/s"
     else:
         achieved, peak, runit = amount / avg_s / 1e12, PEAK_FP32_VALU / 1e12, "TFLOP/s"
     csrc = os.path.join(ROOT, "paper_1509_05054_amd", "csrc")
@@ -174,7 +179,7 @@ def main():
     traffic = read_traffic(dominant, args.workload, digest)
 
     out = {
-        "metric": "signals*iters/s for OMP+JAU (p64 n256 s6)",
+        "metric": f"signals*iters/s for OMP+JAU (p{w.p} n{w.n} s{w.s})",
         "value": value,
         "unit": "signals*iters/s",
         "n_gpus": 1,
@@ -184,10 +189,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if precision == "fp32" else "bf16+f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "p": w.p, "n": w.n, "s": w.s, "m": w.m,
-                   "iters_per_step": iters, "group_size": gs, "precision": "fp32",
+                   "iters_per_step": iters, "group_size": gs, "precision": precision,
                    "rule": "aksvd"},
         "roofline": {"bound": bound, "kernel": dominant, "achieved": achieved, "peak": peak,
                      "unit": runit, "frac": achieved / peak, "traffic": traffic,

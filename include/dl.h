@@ -119,6 +119,13 @@ dl_status dl_gram(const dl_params *prm, const float *D, float *G, dl_stream_t st
 dl_status dl_corr(const dl_params *prm, const float *D, const float *Y, float *A0,
                   dl_stream_t stream);
 
+/* The dense products of the coding stage exactly as dl_omp forms them:
+   G = D D^T ([n][n]) and A0 = Y D^T ([m][n]), in prm->precision (BF16 inputs
+   rounded to nearest-even, FP32 accumulation on the matrix cores, or FP32).
+   Uses the workspace for the BF16 copies. */
+dl_status dl_products(const dl_params *prm, const float *D, const float *Y, float *G, float *A0,
+                      void *ws, size_t ws_bytes, dl_stream_t stream);
+
 /* Step 1 of the DL iteration (Alg. 1): OMP with fixed sparsity s of every
    signal against D, written to X_idx/X_val.  Ties between correlations go to
    the lowest atom index.  A signal stops early when its residual is

@@ -170,3 +170,22 @@ def iterate(Y, D0, s, iters, group_size, rule=RULE_AKSVD, tol_corr=TOL_CORR, tol
     lib.dlo_iterate(p, n, m, s, _dp(Y), _dp(D), int(iters), int(group_size), int(rule),
                     tol_corr, tol_pivot, _ip(idx), _dp(val), _dp(r))
     return D, idx, val, r
+
+
+def iterate_bf16(Y, D0, s, iters, group_size, rule=RULE_AKSVD, tol_corr=TOL_CORR,
+                 tol_pivot=TOL_PIVOT):
+    """The precision variant with its quantisation emulated: every OMP sees D
+    and Y rounded to BF16 (its correlations and Gram entries are formed from
+    those values), the atom update and the error use the FP32 inputs.
+    Returns ``(D, idx, val, rmse[iters])``."""
+    from .bf16 import round_bf16
+    Y32 = np.ascontiguousarray(Y, dtype=np.float32)
+    Yb = round_bf16(Y32)
+    D = normalize(D0)
+    r = np.empty(iters)
+    idx = val = None
+    for k in range(iters):
+        idx, val, _ = omp(round_bf16(D.astype(np.float32)), Yb, s, tol_corr, tol_pivot)
+        D, val, _ = jau_update(Y32, D, idx, val, group_size, rule)
+        r[k] = rmse(Y32, D, idx, val)
+    return D, idx, val, r

@@ -116,11 +116,10 @@ dl_status check_ws(const dl_params *prm, const void *ws, size_t ws_bytes, Ws *ou
     } while (0)
 
 // G and A0 for the coding stage in one launch, in the precision the
-// parameters ask for.
+// parameters ask for; rows of G and A0 have stride ldn.
 dl_status products(const dl_params &prm, const float *D, const float *Y, float *G, float *A0,
-                   const Ws *ws, hipStream_t st)
+                   const Ws *ws, hipStream_t st, int ldn)
 {
-    const int ldn = padded_n(prm.n);
     if (prm.precision == DL_PREC_BF16) {
         uint16_t *Dbf = ws->at<uint16_t>(ws->L.Dbf);
         uint16_t *Ybf = ws->at<uint16_t>(ws->L.Ybf);
@@ -142,7 +141,7 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
 {
     float *G = ws.at<float>(ws.L.G);
     float *A0 = ws.at<float>(ws.L.A0);
-    dl_status rc = products(prm, D, Y, G, A0, &ws, st);
+    dl_status rc = products(prm, D, Y, G, A0, &ws, st, padded_n(prm.n));
     if (rc != DL_OK)
         return rc;
     OmpArgs a;
@@ -320,6 +319,19 @@ dl_status dl_corr(const dl_params *prm, const float *D, const float *Y, float *A
     const GemmF32 c{Y, D, A0, prm->m, prm->n, prm->p, prm->n};
     DL_TRY(launch_gemm_nt_f32(c, nullptr, DL_K_CORR, (hipStream_t)stream));
     return DL_OK;
+}
+
+dl_status dl_products(const dl_params *prm, const float *D, const float *Y, float *G, float *A0,
+                      void *ws, size_t ws_bytes, dl_stream_t stream)
+{
+    if (!valid_params(prm) || !aligned(D, 16) || !aligned(Y, 16) || !aligned(G, 4) ||
+        !aligned(A0, 4))
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    return products(*prm, D, Y, G, A0, &w, (hipStream_t)stream, prm->n);
 }
 
 dl_status dl_omp(const dl_params *prm, const float *D, const float *Y, int32_t *X_idx,

@@ -64,6 +64,7 @@ SIGNATURES = {
     "dl_workspace_init": (ctypes.c_int, [_PP, _vp, ctypes.c_size_t, _vp]),
     "dl_gram": (ctypes.c_int, [_PP, _vp, _vp, _vp]),
     "dl_corr": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp]),
+    "dl_products": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "dl_omp": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "dl_csr": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "dl_jau_update": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -169,6 +170,11 @@ def gram(prm: Params, D, G, stream=None):
 
 def corr(prm: Params, D, Y, A0, stream=None):
     _check(lib().dl_corr(prm.ref(), _ptr(D), _ptr(Y), _ptr(A0), _stream(stream)), "dl_corr")
+
+
+def products(prm: Params, D, Y, G, A0, ws, stream=None):
+    _check(lib().dl_products(prm.ref(), _ptr(D), _ptr(Y), _ptr(G), _ptr(A0), _ptr(ws), ws.numel(),
+                             _stream(stream)), "dl_products")
 
 
 def omp(prm: Params, D, Y, X_idx, X_val, ws, stream=None):
