@@ -1,0 +1,115 @@
+"""Pins of the learned-proposal oracle: gradients by central finite
+differences, Adam's closed-form first step, the removal-cost identity of
+backward elimination, brute force over candidate subsets, top-k order."""
+import itertools
+
+import numpy as np
+
+from oracle import learned
+
+
+def _small_params(rng, sizes=(6, 9, 7, 5)):
+    return [(rng.standard_normal((o, i)) * np.sqrt(2.0 / i), rng.standard_normal(o) * 0.1)
+            for i, o in zip(sizes[:-1], sizes[1:])]
+
+
+def test_mlp_gradients_match_central_differences():
+    rng = np.random.default_rng(0)
+    params = _small_params(rng)
+    X = rng.standard_normal((11, 6))
+    T = (rng.random((11, 5)) < 0.3).astype(float)
+    A, Z = learned.forward(params, X)
+    grads = learned.backward(params, A, Z, T)
+    h = 1e-6
+    for li, (W, b) in enumerate(params):
+        for arr, g in ((W, grads[li][0]), (b, grads[li][1])):
+            num = np.zeros_like(arr)
+            it = np.nditer(arr, flags=["multi_index"])
+            for _ in it:
+                ix = it.multi_index
+                old = arr[ix]
+                arr[ix] = old + h
+                lp = learned.bce_loss(learned.forward(params, X)[1], T)
+                arr[ix] = old - h
+                lm = learned.bce_loss(learned.forward(params, X)[1], T)
+                arr[ix] = old
+                num[ix] = (lp - lm) / (2 * h)
+            rel = np.linalg.norm(num - g) / max(np.linalg.norm(num), 1e-12)
+            assert rel < 1e-6, (li, rel)
+
+
+def test_bce_loss_closed_forms():
+    Z = np.array([[0.0, 2.0], [-3.0, 1.5]])
+    T = np.array([[1.0, 0.0], [0.0, 1.0]])
+    want = np.mean([np.log(2), np.log1p(np.exp(2.0)), np.log1p(np.exp(-3.0)),
+                    np.log1p(np.exp(-1.5))])
+    assert abs(learned.bce_loss(Z, T) - want) < 1e-12
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    """After one step the bias-corrected moments are g and g^2, so every
+    parameter moves by lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(1)
+    params = _small_params(rng)
+    grads = [(rng.standard_normal(W.shape), rng.standard_normal(b.shape)) for W, b in params]
+    new, _ = learned.adam_step(params, grads, learned.adam_init(params), t=1, lr=1e-3)
+    for (W, b), (Wn, bn), (gW, gb) in zip(params, new, grads):
+        np.testing.assert_allclose(W - Wn, 1e-3 * gW / (np.abs(gW) + 1e-8), rtol=1e-12)
+        np.testing.assert_allclose(b - bn, 1e-3 * gb / (np.abs(gb) + 1e-8), rtol=1e-12)
+
+
+def test_removal_cost_equals_explicit_refit():
+    """Dropping atom j from a least-squares fit raises ||r||^2 by exactly
+    c_j^2 / [(D_C^T D_C)^{-1}]_jj."""
+    rng = np.random.default_rng(2)
+    D = rng.standard_normal((30, 16))
+    y = rng.standard_normal(16)
+    C = list(rng.choice(30, size=8, replace=False))
+    A = D[C]
+    Gi = np.linalg.inv(A @ A.T)
+    c = Gi @ (A @ y)
+    r2 = np.sum((y - A.T @ c) ** 2)
+    for q in range(len(C)):
+        keep = [C[t] for t in range(len(C)) if t != q]
+        x, *_ = np.linalg.lstsq(D[keep].T, y, rcond=None)
+        r2q = np.sum((y - D[keep].T @ x) ** 2)
+        assert abs((r2q - r2) - c[q] ** 2 / Gi[q, q]) < 1e-10
+
+
+def test_pruning_never_beats_bruteforce_and_often_matches():
+    rng = np.random.default_rng(3)
+    D = rng.standard_normal((40, 16))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    exact = 0
+    for trial in range(40):
+        y = rng.standard_normal(16)
+        cand = rng.choice(40, size=12, replace=False)
+        sup, c, rn = learned.restricted_ls_prune(D, y, cand, 6)
+        assert len(sup) == 6 and set(sup) <= set(cand)
+        best = min(np.linalg.norm(y - D[list(S)].T @ np.linalg.lstsq(D[list(S)].T, y, rcond=None)[0])
+                   for S in itertools.combinations(cand, 6))
+        assert rn >= best - 1e-12
+        exact += rn <= best + 1e-12
+        np.testing.assert_allclose(c, np.linalg.lstsq(D[sup].T, y, rcond=None)[0], rtol=1e-9,
+                                   atol=1e-12)
+    assert exact >= 10  # greedy elimination finds the optimum in a fair share of cases
+
+
+def test_pruning_recovers_a_planted_support():
+    rng = np.random.default_rng(4)
+    D = rng.standard_normal((50, 32))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    true = rng.choice(50, size=6, replace=False)
+    y = rng.standard_normal(6) @ D[true]
+    others = [j for j in range(50) if j not in true][:6]
+    sup, c, rn = learned.restricted_ls_prune(D, y, np.concatenate([others, true]), 6)
+    assert set(sup) == set(true) and rn < 1e-10
+
+
+def test_top_candidates_order_and_ties():
+    Z = np.array([[0.1, 0.5, 0.5, -1.0, 0.7]])
+    np.testing.assert_array_equal(learned.top_candidates(Z, 3), [[4, 1, 2]])
+
+
+def test_fallback_margin():
+    assert learned.needs_fallback(1.021, 1.0) and not learned.needs_fallback(1.019, 1.0)
