@@ -165,6 +165,56 @@ dl_status dl_rmse(const dl_params *prm, const float *Y, const float *D, const in
 dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, int32_t *X_idx,
                      float *X_val, double *rmse, void *ws, size_t ws_bytes, dl_stream_t stream);
 
+/* ---- learned support proposal ------------------------------------------
+   A network in_dim -> hidden -> hidden -> out_dim with ReLU maps a signal to
+   one logit per atom; it is trained on (signal, OMP support) pairs with the
+   mean binary cross-entropy of the logits against the multi-hot support, and
+   Adam.  Weights and activations are stored in BF16 for the matrix cores
+   (FP32 accumulation); Adam keeps FP32 master weights.  Parameters travel
+   packed as [W1 (hidden x in) | b1 | W2 (hidden x hidden) | b2 |
+   W3 (out x hidden) | b3], row-major, FP32. */
+typedef struct dl_mlp_params {
+    int in_dim;    /* input size (= p), multiple of 8 */
+    int hidden;    /* units per hidden layer, multiple of 32 */
+    int out_dim;   /* outputs (= n), multiple of 8 */
+    int batch;     /* minibatch rows, multiple of 32 */
+    float lr, beta1, beta2, eps;  /* Adam */
+} dl_mlp_params;
+
+/* Packed parameter count, and the workspace bytes of the network (host
+   only; 0 if invalid). */
+size_t dl_mlp_param_count(const dl_mlp_params *q);
+size_t dl_mlp_workspace_size(const dl_mlp_params *q);
+
+/* Load the packed parameters (device) into the workspace, zero the Adam
+   moments and make the BF16 copies. */
+dl_status dl_mlp_init(const dl_mlp_params *q, const float *params, void *ws, size_t ws_bytes,
+                      dl_stream_t stream);
+
+/* One minibatch of q->batch pairs: pair id pairs[b] names signal
+   pairs[b] % m of Y [m][p] (p = in_dim) and the support row pairs[b] of hist
+   ([*][s], -1 = empty slot).  Forward, loss, backward (gradients kept in the
+   workspace); if step > 0, one Adam step with bias corrections for step
+   number `step` (1-based). */
+dl_status dl_mlp_train_step(const dl_mlp_params *q, void *ws, size_t ws_bytes, const float *Y,
+                            int m, int p, const int32_t *hist, int s, const int32_t *pairs,
+                            int step, dl_stream_t stream);
+
+/* Copy the packed FP32 parameters and/or the last step's packed gradients
+   to device buffers (either may be NULL); with loss != NULL, synchronise the
+   stream and store the last step's mean loss (host double). */
+dl_status dl_mlp_read(const dl_mlp_params *q, const void *ws, size_t ws_bytes, float *params,
+                      float *grads, double *loss, dl_stream_t stream);
+
+/* logits [rows][out_dim] (FP32) of the signals X [rows][in_dim]. */
+dl_status dl_mlp_forward(const dl_mlp_params *q, void *ws, size_t ws_bytes, const float *X,
+                         int rows, float *logits, dl_stream_t stream);
+
+/* The k largest entries of every row of logits [rows][cols], largest first,
+   ties to the lower index: out [rows][k] int32 (cols <= 1024, k <= 32). */
+dl_status dl_topk(int rows, int cols, int k, const float *logits, int32_t *out,
+                  dl_stream_t stream);
+
 /* Kernels the library launches, for dl_profile_read. */
 typedef enum {
     DL_K_GRAM = 0,      /* G = D D^T */
@@ -179,6 +229,8 @@ typedef enum {
     DL_K_UPD_EUPDATE,   /* error update between groups */
     DL_K_RMSE,          /* error with the FP64 reduction */
     DL_K_MISC,          /* casts, copies, normalisation, residual */
+    DL_K_MLP,           /* proposal network: GEMMs, loss, optimiser */
+    DL_K_PROPOSE,       /* top-k candidates, restricted least squares, pruning */
     DL_K_COUNT
 } dl_kernel;
 

@@ -149,4 +149,43 @@ hipError_t launch_normalize_rows(float *D, int n, int p, Control *ctl, hipStream
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 hipError_t launch_zero(void *dst, size_t bytes, hipStream_t st);
 
+// ---- proposal network (mlp.hip) -------------------------------------------
+constexpr int kEpiF32 = 0;       // C (fp32) = acc (+ bias)
+constexpr int kEpiBiasRelu = 1;  // C, C^T (bf16) = relu(acc + bias)
+constexpr int kEpiReluMask = 2;  // C, C^T (bf16) = acc where mask > 0, else 0
+struct MlpGemm {
+    const uint16_t *A;  // [M][lda] bf16, K-contiguous
+    const uint16_t *B;  // [N][ldb] bf16, K-contiguous
+    int lda, ldb, M, N, K;  // K % 8 == 0, lda/ldb % 8 == 0
+    int epi;
+    const float *bias;      // [N] or null (only with a single K split)
+    const uint16_t *mask;   // [M][ldmask] (kEpiReluMask)
+    int ldmask;
+    float *Cf;              // kEpiF32 output; split s writes Cf + s * split_stride
+    int ldcf;
+    size_t split_stride;
+    uint16_t *Cb;           // bf16 output [M][ldcb] or null
+    int ldcb;
+    uint16_t *Ct;           // bf16 transposed output [N][ldct] or null
+    int ldct;
+};
+struct AdamHyper {
+    float lr, beta1, beta2, eps, bc1, bc2;  // bc = 1 - beta^t
+};
+hipError_t launch_mlp_gemm(const MlpGemm &g, int splits, hipStream_t st);
+hipError_t launch_sum_splits(const float *part, float *out, size_t count, int splits,
+                             size_t stride, hipStream_t st);
+hipError_t launch_rowsum_bf16(const uint16_t *X, float *out, int rows, int cols, hipStream_t st);
+hipError_t launch_gather_batch(const float *Y, int m, int p, const int32_t *pairs, int B,
+                               uint16_t *Xb, uint16_t *Xbt, hipStream_t st);
+hipError_t launch_gather_rows(const float *X, int rows, int cols, uint16_t *Xb, hipStream_t st);
+hipError_t launch_bce(const float *Z, int out_dim, const int32_t *hist, int s,
+                      const int32_t *pairs, int B, uint16_t *dZ, uint16_t *dZt, double *loss_rows,
+                      hipStream_t st);
+hipError_t launch_adam(float *w, const float *g, float *m1, float *m2, int rows, int cols,
+                       uint16_t *wb, uint16_t *wbt, const AdamHyper &h, int do_step,
+                       hipStream_t st);
+hipError_t launch_topk(const float *logits, int rows, int cols, int k, int32_t *out,
+                       hipStream_t st);
+
 }  // namespace dlk

@@ -72,6 +72,15 @@ SIGNATURES = {
     "dl_iterate": (ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp]),
     "dl_read_stats": (ctypes.c_int, [_PP, _vp, ctypes.c_size_t, ctypes.POINTER(Stats), _vp]),
+    "dl_mlp_param_count": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "dl_mlp_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "dl_mlp_init": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "dl_mlp_train_step": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int, ctypes.c_int,
+                                         _vp, ctypes.c_int, _vp, ctypes.c_int, _vp]),
+    "dl_mlp_read": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp,
+                                   ctypes.POINTER(ctypes.c_double), _vp]),
+    "dl_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int, _vp, _vp]),
+    "dl_topk": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "dl_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
@@ -79,7 +88,7 @@ SIGNATURES = {
 
 # kernel ids of dl_profile_read (enum dl_kernel)
 KERNELS = ["gram", "corr", "omp", "csr_count", "csr_scan", "csr_scatter", "upd_pass1",
-           "upd_reduce", "upd_pass2", "upd_eupdate", "rmse", "misc"]
+           "upd_reduce", "upd_pass2", "upd_eupdate", "rmse", "misc", "mlp", "propose"]
 
 
 def lib():
@@ -200,6 +209,71 @@ def rmse(prm: Params, Y, D, X_idx, X_val, out, ws, stream=None):
 def iterate(prm: Params, Y, D, iters, X_idx, X_val, rmse_out, ws, stream=None):
     _check(lib().dl_iterate(prm.ref(), _ptr(Y), _ptr(D), int(iters), _ptr(X_idx), _ptr(X_val),
                             _ptr(rmse_out), _ptr(ws), ws.numel(), _stream(stream)), "dl_iterate")
+
+
+class _MlpParams(ctypes.Structure):
+    _fields_ = [("in_dim", ctypes.c_int), ("hidden", ctypes.c_int), ("out_dim", ctypes.c_int),
+                ("batch", ctypes.c_int), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+@dataclass
+class MlpParams:
+    in_dim: int
+    hidden: int
+    out_dim: int
+    batch: int = 4096
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def ref(self):
+        self._c = _MlpParams(self.in_dim, self.hidden, self.out_dim, self.batch, self.lr,
+                             self.beta1, self.beta2, self.eps)
+        return ctypes.cast(ctypes.pointer(self._c), ctypes.c_void_p)
+
+
+def mlp_param_count(q: MlpParams) -> int:
+    n = lib().dl_mlp_param_count(q.ref())
+    if n == 0:
+        raise DLError(DL_EINVAL, "dl_mlp_param_count")
+    return int(n)
+
+
+def mlp_workspace(q: MlpParams, params, device="cuda") -> torch.Tensor:
+    """Allocate the network workspace and load the packed FP32 parameters."""
+    size = lib().dl_mlp_workspace_size(q.ref())
+    if size == 0:
+        raise DLError(DL_EINVAL, "dl_mlp_workspace_size")
+    ws = torch.empty(int(size), dtype=torch.uint8, device=device)
+    _check(lib().dl_mlp_init(q.ref(), _ptr(params), _ptr(ws), ws.numel(), _stream()), "dl_mlp_init")
+    return ws
+
+
+def mlp_train_step(q: MlpParams, ws, Y, hist, pairs, step, stream=None):
+    m, p = Y.shape
+    s = hist.shape[1]
+    _check(lib().dl_mlp_train_step(q.ref(), _ptr(ws), ws.numel(), _ptr(Y), m, p, _ptr(hist), s,
+                                   _ptr(pairs), int(step), _stream(stream)), "dl_mlp_train_step")
+
+
+def mlp_read(q: MlpParams, ws, params=None, grads=None, want_loss=False, stream=None):
+    loss = ctypes.c_double(0.0)
+    _check(lib().dl_mlp_read(q.ref(), _ptr(ws), ws.numel(), _ptr(params), _ptr(grads),
+                             ctypes.byref(loss) if want_loss else None, _stream(stream)),
+           "dl_mlp_read")
+    return loss.value if want_loss else None
+
+
+def mlp_forward(q: MlpParams, ws, X, logits, stream=None):
+    _check(lib().dl_mlp_forward(q.ref(), _ptr(ws), ws.numel(), _ptr(X), X.shape[0], _ptr(logits),
+                                _stream(stream)), "dl_mlp_forward")
+
+
+def topk(logits, k, out, stream=None):
+    rows, cols = logits.shape
+    _check(lib().dl_topk(rows, cols, int(k), _ptr(logits), _ptr(out), _stream(stream)), "dl_topk")
 
 
 def profile_enable(on: bool, max_launches: int = 1 << 16):

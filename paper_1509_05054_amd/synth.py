@@ -34,6 +34,8 @@ __all__ = [
     "initial_dictionary",
     "workload",
     "batched_problems",
+    "mlp_params",
+    "unpack_mlp",
     "WORKLOADS",
 ]
 
@@ -207,6 +209,30 @@ def workload(name: str, m: int | None = None) -> Workload:
         extra = {}
     return Workload(name=name, p=cfg["p"], n=cfg["n"], s=cfg["s"], m=mm, iters=cfg["iters"],
                     group_sizes=tuple(cfg["group_sizes"]), Y=Y, D0=D0, extra=extra)
+
+
+def mlp_params(sizes, seed):
+    """Initial weights of the proposal network, packed [W1 b1 W2 b2 W3 b3]
+    (W_l of shape [out][in], row-major), float32: He-normal weights
+    N(0, 2 / fan_in), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in zip(sizes[:-1], sizes[1:]):
+        parts.append((rng.standard_normal((fan_out, fan_in)) * math.sqrt(2.0 / fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unpack_mlp(vec, sizes):
+    """Split a packed parameter vector into [(W, b), ...]."""
+    out, off = [], 0
+    for fan_in, fan_out in zip(sizes[:-1], sizes[1:]):
+        W = vec[off:off + fan_in * fan_out].reshape(fan_out, fan_in)
+        off += fan_in * fan_out
+        b = vec[off:off + fan_out]
+        off += fan_out
+        out.append((W, b))
+    return out
 
 
 def batched_problems(count: int, seed: int, m_scale: float = 1.0):
