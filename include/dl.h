@@ -167,9 +167,10 @@ dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, 
 
 /* ---- learned support proposal ------------------------------------------
    A network in_dim -> hidden -> hidden -> out_dim with ReLU maps a signal to
-   one logit per atom; it is trained on (signal, OMP support) pairs with the
-   mean binary cross-entropy of the logits against the multi-hot support, and
-   Adam.  Weights and activations are stored in BF16 for the matrix cores
+   one logit per atom; it sees the signal scaled to unit norm (the OMP support
+   depends on its direction only).  It is trained on (signal, OMP support)
+   pairs with the mean binary cross-entropy of the logits against the
+   multi-hot support, positive terms weighted by pos_weight, and Adam.  Weights and activations are stored in BF16 for the matrix cores
    (FP32 accumulation); Adam keeps FP32 master weights.  Parameters travel
    packed as [W1 (hidden x in) | b1 | W2 (hidden x hidden) | b2 |
    W3 (out x hidden) | b3], row-major, FP32. */
@@ -179,6 +180,8 @@ typedef struct dl_mlp_params {
     int out_dim;   /* outputs (= n), multiple of 8 */
     int batch;     /* minibatch rows, multiple of 32 */
     float lr, beta1, beta2, eps;  /* Adam */
+    float pos_weight;  /* weight of the loss terms of support atoms, > 0;
+                          (n - s) / s balances the s positives of a row */
 } dl_mlp_params;
 
 /* Packed parameter count, and the workspace bytes of the network (host
@@ -245,6 +248,47 @@ dl_status dl_profile_enable(int on, int max_launches);
    count into ms[k] / launches[k] for k < count (count <= DL_K_COUNT), then
    clear the record (timing stays enabled). */
 dl_status dl_profile_read(double *ms, long long *launches, int count);
+
+/* As dl_iterate, and also record every iteration's OMP supports in hist
+   [iters][m][s] (device, may be NULL) and the residual norm ||y - D X|| of
+   every signal's last OMP in rref [m] (device, may be NULL): the training
+   pairs and reference residuals of the learned proposal. */
+dl_status dl_iterate_record(const dl_params *prm, const float *Y, float *D, int iters,
+                            int32_t *X_idx, float *X_val, double *rmse, int32_t *hist,
+                            float *rref, void *ws, size_t ws_bytes, dl_stream_t stream);
+
+/* Learned support proposal for the coding stage. */
+typedef struct dl_proposal {
+    const int32_t *cand;  /* [m][k] candidate atoms per signal (device), e.g. dl_topk */
+    int k;                /* candidates per signal: 8, 12 or 16, >= s */
+    float margin;         /* hand a signal back to OMP when its residual exceeds
+                             (1 + margin) times its reference OMP residual (0.02) */
+    int audit_every;      /* code every signal with OMP on every audit_every-th
+                             iteration, refreshing the references (0 = never; the
+                             last iteration is never an audit) */
+} dl_proposal;
+
+/* Bytes of the proposal workspace (fallback list and gathered signals). */
+size_t dl_proposal_workspace_size(const dl_params *prm);
+
+/* The coding stage of dl_iterate_proposed on its own (one call, no update):
+   X_idx/X_val of every signal from the proposal or, when rejected, from OMP;
+   rref is refreshed for the rejected signals. */
+dl_status dl_code_proposed(const dl_params *prm, const dl_proposal *pr, const float *D,
+                           const float *Y, float *rref, int32_t *X_idx, float *X_val, void *ws,
+                           size_t ws_bytes, void *pws, size_t pws_bytes, dl_stream_t stream);
+
+/* `iters` DL iterations whose coding stage uses the proposal: least squares
+   restricted to the k candidates, backward elimination to s atoms (drop the
+   atom whose removal raises the residual least), and OMP for the signals whose
+   residual exceeds the margin (their reference residuals in rref [m] are
+   refreshed); the atom update and the error are those of dl_iterate.  FP32
+   only.  Arguments otherwise as dl_iterate; the fallback count is in the
+   workspace statistics. */
+dl_status dl_iterate_proposed(const dl_params *prm, const dl_proposal *pr, const float *Y,
+                              float *D, int iters, float *rref, int32_t *X_idx, float *X_val,
+                              double *rmse, void *ws, size_t ws_bytes, void *pws, size_t pws_bytes,
+                              dl_stream_t stream);
 
 /* Synchronise `stream` and copy the workspace counters to *out (host).
    Returns DL_ENUMERIC if any non-finite value was counted, else DL_OK. */

@@ -1,9 +1,11 @@
 """FP64 oracle for the learned support proposal (test infrastructure only).
 
-The proposal network maps a signal y (p = 64) to one logit per atom (n = 256)
+The proposal network maps a signal's direction y / ||y|| (p = 64; the OMP
+support of y does not depend on its scale) to one logit per atom (n = 256)
 through two ReLU hidden layers of 512 units; it is trained with a multi-label
-loss (mean binary cross-entropy on the logits, targets = the atoms OMP chose)
-and Adam.  A proposal keeps the 2s atoms with the largest logits; least
+loss (mean binary cross-entropy on the logits, targets = the atoms OMP chose,
+positives weighted by pos_weight, e.g. (n - s) / s to balance the s positives
+against the n - s negatives) and Adam.  A proposal keeps the 2s atoms with the largest logits; least
 squares restricted to them is pruned greedily (backward elimination) to s
 atoms; the signal goes back to OMP when the pruned residual exceeds the
 reference OMP residual by more than a stated margin.
@@ -21,6 +23,13 @@ SIZES = (64, 512, 512, 256)
 
 
 # --------------------------------------------------------------- network
+def network_input(Y):
+    """Rows of Y scaled to unit norm (zero rows stay zero)."""
+    Y = np.asarray(Y, np.float64)
+    nrm = np.linalg.norm(Y, axis=1, keepdims=True)
+    return Y / np.where(nrm > 0, nrm, 1.0)
+
+
 def forward(params, X, emulate_bf16=False):
     """params = [(W1, b1), (W2, b2), (W3, b3)], W_l of shape [out][in].
     Returns (hidden activations [A0=X, A1, A2], logits Z).  With
@@ -48,16 +57,17 @@ def targets(idx, n):
     return T
 
 
-def bce_loss(Z, T):
-    """Mean over all entries of the binary cross-entropy of sigmoid(Z) vs T,
-    written with logits: softplus(z) - t z."""
-    return float(np.mean(np.logaddexp(0.0, Z) - T * Z))
+def bce_loss(Z, T, pos_weight=1.0):
+    """Mean over all entries of the binary cross-entropy of sigmoid(Z) vs T
+    with positives weighted: w t softplus(-z) + (1 - t) softplus(z)."""
+    return float(np.mean(pos_weight * T * np.logaddexp(0.0, -Z) + (1 - T) * np.logaddexp(0.0, Z)))
 
 
-def backward(params, A, Z, T):
+def backward(params, A, Z, T, pos_weight=1.0):
     """Gradients of bce_loss w.r.t. every (W, b), by the chain rule."""
     n_el = Z.size
-    dZ = (1.0 / (1.0 + np.exp(-Z)) - T) / n_el
+    sig = 1.0 / (1.0 + np.exp(-Z))
+    dZ = (sig * (1 - T) - (1 - sig) * T * pos_weight) / n_el
     grads = [None] * len(params)
     d = dZ
     for li in range(len(params) - 1, -1, -1):

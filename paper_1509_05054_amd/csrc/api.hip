@@ -118,36 +118,57 @@ dl_status check_ws(const dl_params *prm, const void *ws, size_t ws_bytes, Ws *ou
 // G and A0 for the coding stage in one launch, in the precision the
 // parameters ask for; rows of G and A0 have stride ldn.
 dl_status products(const dl_params &prm, const float *D, const float *Y, float *G, float *A0,
-                   const Ws *ws, hipStream_t st, int ldn)
+                   const Ws *ws, hipStream_t st, int ldn, const int32_t *m_dev = nullptr)
 {
     if (prm.precision == DL_PREC_BF16) {
         uint16_t *Dbf = ws->at<uint16_t>(ws->L.Dbf);
         uint16_t *Ybf = ws->at<uint16_t>(ws->L.Ybf);
         DL_TRY(launch_cast_bf16(D, Dbf, (size_t)prm.n * prm.p, st));
         DL_TRY(launch_cast_bf16(Y, Ybf, (size_t)prm.m * prm.p, st));
-        const GemmBF16 g{Dbf, Dbf, G, prm.n, prm.n, prm.p, ldn};
-        const GemmBF16 c{Ybf, Dbf, A0, prm.m, prm.n, prm.p, ldn};
-        DL_TRY(launch_gemm_nt_bf16(g, &c, DL_K_CORR, st));
+        const GemmBF16 g{Dbf, Dbf, G, prm.n, prm.n, prm.p, ldn, nullptr};
+        const GemmBF16 c{Ybf, Dbf, A0, prm.m, prm.n, prm.p, ldn, m_dev};
+        if (G && A0)
+            DL_TRY(launch_gemm_nt_bf16(g, &c, DL_K_CORR, st));
+        else if (G)
+            DL_TRY(launch_gemm_nt_bf16(g, nullptr, DL_K_GRAM, st));
+        else if (A0)
+            DL_TRY(launch_gemm_nt_bf16(c, nullptr, DL_K_CORR, st));
     } else {
-        const GemmF32 g{D, D, G, prm.n, prm.n, prm.p, ldn};
-        const GemmF32 c{Y, D, A0, prm.m, prm.n, prm.p, ldn};
-        DL_TRY(launch_gemm_nt_f32(g, &c, DL_K_CORR, st));
+        const GemmF32 g{D, D, G, prm.n, prm.n, prm.p, ldn, nullptr};
+        const GemmF32 c{Y, D, A0, prm.m, prm.n, prm.p, ldn, m_dev};
+        if (G && A0)
+            DL_TRY(launch_gemm_nt_f32(g, &c, DL_K_CORR, st));
+        else if (G)
+            DL_TRY(launch_gemm_nt_f32(g, nullptr, DL_K_GRAM, st));
+        else if (A0)
+            DL_TRY(launch_gemm_nt_f32(c, nullptr, DL_K_CORR, st));
     }
     return DL_OK;
 }
 
+struct OmpExtra {
+    const float *Y = nullptr;      // compact signals (default: the caller's Y)
+    const int32_t *m_dev = nullptr;
+    const int32_t *rowmap = nullptr;
+    float *rnorm = nullptr;
+    bool products = true;          // form G and A0 here
+};
+
 dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t *idx, float *val,
-                  const Ws &ws, hipStream_t st)
+                  const Ws &ws, hipStream_t st, const OmpExtra &x = OmpExtra())
 {
     float *G = ws.at<float>(ws.L.G);
     float *A0 = ws.at<float>(ws.L.A0);
-    dl_status rc = products(prm, D, Y, G, A0, &ws, st, padded_n(prm.n));
-    if (rc != DL_OK)
-        return rc;
+    const float *Yin = x.Y ? x.Y : Y;
+    if (x.products) {
+        dl_status rc = products(prm, D, Yin, G, A0, &ws, st, padded_n(prm.n));
+        if (rc != DL_OK)
+            return rc;
+    }
     OmpArgs a;
     a.A0 = A0;
     a.G = G;
-    a.Y = Y;
+    a.Y = Yin;
     a.D = D;
     a.idx = idx;
     a.val = val;
@@ -158,6 +179,9 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
     a.m = prm.m;
     a.s = prm.s;
     a.ldn = padded_n(prm.n);
+    a.m_dev = x.m_dev;
+    a.rowmap = x.rowmap;
+    a.rnorm = x.rnorm;
     a.lanes_per_signal = prm.omp_lanes_per_signal;
     a.atoms_per_lane = prm.omp_atoms_per_lane;
     a.pivot_fp64 = prm.pivot_fp64_threshold;
@@ -398,8 +422,9 @@ dl_status dl_rmse(const dl_params *prm, const float *Y, const float *D, const in
     return run_rmse(*prm, Y, D, X_idx, X_val, rmse_out, w, (hipStream_t)stream);
 }
 
-dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, int32_t *X_idx,
-                     float *X_val, double *rmse, void *ws, size_t ws_bytes, dl_stream_t stream)
+static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, int iters,
+                              int32_t *X_idx, float *X_val, double *rmse, int32_t *hist,
+                              float *rref, void *ws, size_t ws_bytes, dl_stream_t stream)
 {
     if (!valid_params(prm) || iters < 0 || !aligned(Y, 16) || !aligned(D, 16) ||
         !aligned(X_idx, 4) || !aligned(X_val, 4) || (iters > 0 && !aligned(rmse, 8)))
@@ -416,10 +441,161 @@ dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, 
     float *val_ws = w.at<float>(w.L.val_ws);
     // the dictionary alternates between the caller's buffer and the workspace
     float *Dcur = D, *Dnext = Dws;
+    const size_t ms = (size_t)q.m * q.s;
     for (int k = 0; k < iters; ++k) {
-        rc = run_omp(q, Dcur, Y, X_idx, val_ws, w, st);
+        OmpExtra x;
+        x.rnorm = rref;
+        rc = run_omp(q, Dcur, Y, X_idx, val_ws, w, st, x);
         if (rc != DL_OK)
             return rc;
+        if (hist)
+            DL_TRY(launch_copy(X_idx, hist + (size_t)k * ms, 4 * ms, st));
+        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st);
+        if (rc != DL_OK)
+            return rc;
+        rc = run_rmse(q, Y, Dnext, X_idx, X_val, rmse + k, w, st);
+        if (rc != DL_OK)
+            return rc;
+        float *t = Dcur;
+        Dcur = Dnext;
+        Dnext = t;
+    }
+    if (Dcur != D)
+        DL_TRY(launch_copy(Dcur, D, sizeof(float) * (size_t)q.n * q.p, st));
+    return DL_OK;
+}
+
+dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, int32_t *X_idx,
+                     float *X_val, double *rmse, void *ws, size_t ws_bytes, dl_stream_t stream)
+{
+    return iterate_impl(prm, Y, D, iters, X_idx, X_val, rmse, nullptr, nullptr, ws, ws_bytes,
+                        stream);
+}
+
+dl_status dl_iterate_record(const dl_params *prm, const float *Y, float *D, int iters,
+                            int32_t *X_idx, float *X_val, double *rmse, int32_t *hist,
+                            float *rref, void *ws, size_t ws_bytes, dl_stream_t stream)
+{
+    if ((hist && !aligned(hist, 4)) || (rref && !aligned(rref, 4)))
+        return DL_EINVAL;
+    return iterate_impl(prm, Y, D, iters, X_idx, X_val, rmse, hist, rref, ws, ws_bytes, stream);
+}
+
+// Coding stage with the proposal: Gram matrix, restricted least squares and
+// pruning for every signal, OMP for the rejected ones.
+static dl_status code_proposed(const dl_params &q, const dl_proposal &pr, const float *D,
+                               const float *Y, float *rref, int32_t *X_idx, float *val,
+                               const Ws &w, void *pws, hipStream_t st)
+{
+    int32_t *fb_count = (int32_t *)pws;
+    int32_t *fb_list = (int32_t *)((char *)pws + align256(sizeof(int32_t) * 64));
+    float *Y_fb = (float *)((char *)fb_list + align256(sizeof(int32_t) * (size_t)q.m));
+    float *G = w.at<float>(w.L.G);
+    dl_status rc = products(q, D, Y, G, nullptr, &w, st, padded_n(q.n));
+    if (rc != DL_OK)
+        return rc;
+    DL_TRY(launch_zero(fb_count, 4, st));
+    ProposeArgs a;
+    a.Y = Y;
+    a.D = D;
+    a.G = G;
+    a.cand = pr.cand;
+    a.rref = rref;
+    a.idx = X_idx;
+    a.val = val;
+    a.E = w.at<float>(w.L.E);
+    a.fb_list = fb_list;
+    a.fb_count = fb_count;
+    a.ctl = w.ctl();
+    a.p = q.p;
+    a.n = q.n;
+    a.m = q.m;
+    a.s = q.s;
+    a.ldn = padded_n(q.n);
+    a.margin = pr.margin;
+    DL_TRY(launch_ls_prune(a, pr.k, st));
+    // the rejected signals are coded by OMP
+    DL_TRY(launch_gather_list(Y, q.p, fb_list, fb_count, q.m, Y_fb, st));
+    rc = products(q, D, Y_fb, nullptr, w.at<float>(w.L.A0), &w, st, padded_n(q.n), fb_count);
+    if (rc != DL_OK)
+        return rc;
+    OmpExtra x;
+    x.Y = Y_fb;
+    x.m_dev = fb_count;
+    x.rowmap = fb_list;
+    x.rnorm = rref;
+    x.products = false;
+    return run_omp(q, D, Y, X_idx, val, w, st, x);
+}
+
+static bool proposal_ok(const dl_params *prm, const dl_proposal *pr, const void *pws,
+                        size_t pws_bytes)
+{
+    return pr && aligned(pr->cand, 4) && (pr->k == 8 || pr->k == 12 || pr->k == 16) &&
+           pr->k >= prm->s && pr->margin >= 0.f && pr->audit_every >= 0 &&
+           prm->precision == DL_PREC_FP32 && aligned(pws, 256);
+}
+
+dl_status dl_code_proposed(const dl_params *prm, const dl_proposal *pr, const float *D,
+                           const float *Y, float *rref, int32_t *X_idx, float *X_val, void *ws,
+                           size_t ws_bytes, void *pws, size_t pws_bytes, dl_stream_t stream)
+{
+    if (!valid_params(prm) || !proposal_ok(prm, pr, pws, pws_bytes) || !aligned(D, 16) ||
+        !aligned(Y, 16) || !aligned(rref, 4) || !aligned(X_idx, 4) || !aligned(X_val, 4))
+        return DL_EINVAL;
+    if (pws_bytes < dl_proposal_workspace_size(prm))
+        return DL_EWORKSPACE;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    return code_proposed(*prm, *pr, D, Y, rref, X_idx, X_val, w, pws, (hipStream_t)stream);
+}
+
+size_t dl_proposal_workspace_size(const dl_params *prm)
+{
+    if (!valid_params(prm))
+        return 0;
+    const size_t m = prm->m, p = prm->p;
+    return align256(sizeof(int32_t) * 64) + align256(sizeof(int32_t) * m) +
+           align256(sizeof(float) * m * p);
+}
+
+dl_status dl_iterate_proposed(const dl_params *prm, const dl_proposal *pr, const float *Y,
+                              float *D, int iters, float *rref, int32_t *X_idx, float *X_val,
+                              double *rmse, void *ws, size_t ws_bytes, void *pws, size_t pws_bytes,
+                              dl_stream_t stream)
+{
+    if (!valid_params(prm) || !proposal_ok(prm, pr, pws, pws_bytes) || iters < 0 ||
+        !aligned(Y, 16) || !aligned(D, 16) || !aligned(X_idx, 4) || !aligned(X_val, 4) ||
+        !aligned(rref, 4) || (iters > 0 && !aligned(rmse, 8)))
+        return DL_EINVAL;
+    if (pws_bytes < dl_proposal_workspace_size(prm))
+        return DL_EWORKSPACE;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const dl_params &q = *prm;
+    DL_TRY(launch_zero(w.ctl(), sizeof(Control), st));
+    DL_TRY(launch_normalize_rows(D, q.n, q.p, w.ctl(), st));
+    float *Dws = w.at<float>(w.L.Dn);
+    float *val_ws = w.at<float>(w.L.val_ws);
+    float *Dcur = D, *Dnext = Dws;
+    for (int k = 0; k < iters; ++k) {
+        const bool audit = pr->audit_every > 0 && (k + 1) % pr->audit_every == 0 && k + 1 < iters;
+        if (audit) {
+            OmpExtra x;
+            x.rnorm = rref;
+            rc = run_omp(q, Dcur, Y, X_idx, val_ws, w, st, x);
+            if (rc != DL_OK)
+                return rc;
+        } else {
+            rc = code_proposed(q, *pr, Dcur, Y, rref, X_idx, val_ws, w, pws, st);
+            if (rc != DL_OK)
+                return rc;
+        }
         rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st);
         if (rc != DL_OK)
             return rc;

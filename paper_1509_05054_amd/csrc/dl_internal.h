@@ -69,11 +69,13 @@ struct GemmF32 {
     const float *A, *B;
     float *C;
     int M, N, K, ldc;
+    const int32_t *M_dev;  // optional: rows read on the device (<= M)
 };
 struct GemmBF16 {  // BF16 inputs as uint16 bit patterns
     const uint16_t *A, *B;
     float *C;
     int M, N, K, ldc;
+    const int32_t *M_dev;
 };
 hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st);
 hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st);
@@ -91,6 +93,9 @@ struct OmpArgs {
     Control *ctl;
     int p, n, m, s;
     int ldn;               // leading dimension of G and A0 rows (multiple of 4, >= n)
+    const int32_t *m_dev;  // optional: signal count read on the device (<= m)
+    const int32_t *rowmap; // optional: output row of compact signal i
+    float *rnorm;          // optional: ||y - D x|| per output row
     int lanes_per_signal;  // 4..64, or 0 for the default
     int atoms_per_lane;    // 8 or 16, or 0 for the default (16)
     float pivot_fp64, tol_corr, tol_pivot;
@@ -181,11 +186,28 @@ hipError_t launch_gather_batch(const float *Y, int m, int p, const int32_t *pair
 hipError_t launch_gather_rows(const float *X, int rows, int cols, uint16_t *Xb, hipStream_t st);
 hipError_t launch_bce(const float *Z, int out_dim, const int32_t *hist, int s,
                       const int32_t *pairs, int B, uint16_t *dZ, uint16_t *dZt, double *loss_rows,
-                      hipStream_t st);
+                      float w_pos, hipStream_t st);
 hipError_t launch_adam(float *w, const float *g, float *m1, float *m2, int rows, int cols,
                        uint16_t *wb, uint16_t *wbt, const AdamHyper &h, int do_step,
                        hipStream_t st);
 hipError_t launch_topk(const float *logits, int rows, int cols, int k, int32_t *out,
                        hipStream_t st);
+
+struct ProposeArgs {
+    const float *Y, *D, *G;    // [m][p], [n][p], [n][ldn]
+    const int32_t *cand;       // [m][k2]
+    const float *rref;         // [m] reference OMP residual norms
+    int32_t *idx;              // [m][s]
+    float *val;                // [m][s]
+    float *E;                  // [m][p]
+    int32_t *fb_list;          // [m] signals handed back to OMP
+    int32_t *fb_count;         // one int (zeroed before the launch)
+    Control *ctl;
+    int p, n, m, s, ldn;
+    float margin;
+};
+hipError_t launch_ls_prune(const ProposeArgs &a, int k2, hipStream_t st);
+hipError_t launch_gather_list(const float *src, int p, const int32_t *list, const int32_t *count,
+                              int cap, float *rows, hipStream_t st);
 
 }  // namespace dlk

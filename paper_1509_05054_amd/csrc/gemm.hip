@@ -48,6 +48,10 @@ __device__ inline bool pick_problem(const P &p0, const P &p1, int tiles_y0, P &o
 {
     const int by = blockIdx.y;
     out = by < tiles_y0 ? p0 : p1;
+    if (out.M_dev) {
+        const int md = *out.M_dev;
+        out.M = md < out.M ? md : out.M;
+    }
     const int ty = by < tiles_y0 ? by : by - tiles_y0;
     row0 = ty * kBlockM;
     col0 = blockIdx.x * kBlockN;

@@ -1,14 +1,16 @@
 // Support-proposal network: in -> H -> H -> out with ReLU, BF16 storage of
 // weights and activations, FP32 accumulation on the BF16 matrix cores, FP32
 // master weights and Adam state.  Trained with a multi-label loss (mean binary
-// cross-entropy on the logits) on (signal, OMP support) pairs.
+// cross-entropy on the logits, positives weighted by w_pos) on (signal, OMP
+// support) pairs.  The network sees each signal scaled to unit norm: the OMP
+// support depends only on the signal's direction.
 //
 // Every product is an "NT" GEMM C[M][N] = A[M][K] B[N][K]^T with both operands
 // K-contiguous BF16; the backward pass gets K-contiguous operands because the
 // forward epilogues also write transposed copies of the activations, and the
 // weights are kept transposed in BF16 as well:
 //   forward   H1 = relu(X W1^T + b1), H2 = relu(H1 W2^T + b2), Z = H2 W3^T + b3
-//   loss      dZ = (sigmoid(Z) - T) / (B * out)
+//   loss      dZ = (sigmoid(Z) (1 - T) - (1 - sigmoid(Z)) T w_pos) / (B * out)
 //   backward  dA2 = (dZ W3) . [H2 > 0]     A = dZ,   B = W3^T
 //             dW3 = dZ^T H2                A = dZ^T, B = H2^T   (split over K)
 //             dA1 = (dA2 W2) . [H1 > 0]    A = dA2,  B = W2^T
@@ -170,31 +172,55 @@ __global__ __launch_bounds__(256) void rowsum_bf16_kernel(const uint16_t *__rest
         out[row] = acc;
 }
 
-// Minibatch: X rows (BF16) and their transpose from the chosen pairs; pair id
-// q names signal q % m and label row q of `hist`.
-__global__ void gather_batch_kernel(const float *__restrict__ Y, int m, int p,
-                                    const int32_t *__restrict__ pairs, int B,
-                                    uint16_t *__restrict__ Xb, uint16_t *__restrict__ Xbt)
+// 1 / ||row|| in FP32 for one wave's row (0 for a zero row); every lane gets it.
+__device__ inline float inv_row_norm(const float *__restrict__ row, int p, int lane)
 {
-    const size_t total = (size_t)B * p;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int b = (int)(e / p), q = (int)(e % p);
-        const int sig = (int)((unsigned)pairs[b] % (unsigned)m);
-        const uint16_t h = f2bf(Y[(size_t)sig * p + q]);
-        Xb[e] = h;
+    float ss = 0.f;
+    for (int q = lane; q < p; q += 64)
+        ss += row[q] * row[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        ss += __shfl_xor(ss, off);
+    return ss > 0.f ? 1.0f / sqrtf(ss) : 0.f;
+}
+
+// Minibatch: unit-norm X rows (BF16) and their transpose from the chosen
+// pairs, one wave per row; pair id q names signal q % m and label row q of
+// `hist`.
+__global__ __launch_bounds__(256) void gather_batch_kernel(const float *__restrict__ Y, int m,
+                                                           int p,
+                                                           const int32_t *__restrict__ pairs,
+                                                           int B, uint16_t *__restrict__ Xb,
+                                                           uint16_t *__restrict__ Xbt)
+{
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= B)
+        return;
+    const int sig = (int)((unsigned)pairs[b] % (unsigned)m);
+    const float *row = Y + (size_t)sig * p;
+    const float inv = inv_row_norm(row, p, lane);
+    for (int q = lane; q < p; q += 64) {
+        const uint16_t h = f2bf(row[q] * inv);
+        Xb[(size_t)b * p + q] = h;
         if (Xbt)
             Xbt[(size_t)q * B + b] = h;
     }
 }
 
-// Consecutive FP32 rows -> BF16 (inference input).
-__global__ void gather_rows_kernel(const float *__restrict__ X, size_t count,
-                                   uint16_t *__restrict__ Xb)
+// Consecutive FP32 rows -> unit-norm BF16 rows (inference input), one wave
+// per row.
+__global__ __launch_bounds__(256) void gather_rows_kernel(const float *__restrict__ X, int rows,
+                                                          int cols, uint16_t *__restrict__ Xb)
 {
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-         e += (size_t)gridDim.x * blockDim.x)
-        Xb[e] = f2bf(X[e]);
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows)
+        return;
+    const float *row = X + (size_t)r * cols;
+    const float inv = inv_row_norm(row, cols, lane);
+    for (int q = lane; q < cols; q += 64)
+        Xb[(size_t)r * cols + q] = f2bf(row[q] * inv);
 }
 
 // Loss and its gradient w.r.t. the logits, one wave per minibatch row.
@@ -203,7 +229,7 @@ __global__ __launch_bounds__(256) void bce_kernel(const float *__restrict__ Z, i
                                                   const int32_t *__restrict__ pairs, int B,
                                                   uint16_t *__restrict__ dZ,
                                                   uint16_t *__restrict__ dZt,
-                                                  double *__restrict__ loss_rows)
+                                                  double *__restrict__ loss_rows, float w_pos)
 {
     const int lane = threadIdx.x & 63;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -218,12 +244,13 @@ __global__ __launch_bounds__(256) void bce_kernel(const float *__restrict__ Z, i
             t |= lab[q] == c;
         const float z = Z[(size_t)b * out_dim + c];
         const float sig = 1.0f / (1.0f + expf(-z));
-        const float d = (sig - (t ? 1.f : 0.f)) * scale;
+        const float d = (t ? -(1.0f - sig) * w_pos : sig) * scale;
         const uint16_t h = f2bf(d);
         dZ[(size_t)b * out_dim + c] = h;
         dZt[(size_t)c * B + b] = h;
-        // softplus(z) - t z, computed stably
-        l += (double)(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - (t ? z : 0.f));
+        // positives: w_pos softplus(-z); negatives: softplus(z) (stable forms)
+        const float sp = log1pf(expf(-fabsf(z)));
+        l += t ? (double)w_pos * (double)(fmaxf(-z, 0.f) + sp) : (double)(fmaxf(z, 0.f) + sp);
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
@@ -304,17 +331,16 @@ hipError_t launch_gather_batch(const float *Y, int m, int p, const int32_t *pair
                                uint16_t *Xb, uint16_t *Xbt, hipStream_t st)
 {
     prof_begin(DL_K_MLP, st);
-    hipLaunchKernelGGL(gather_batch_kernel, dim3(grid1((size_t)B * p, 4096)), dim3(256), 0, st, Y,
-                       m, p, pairs, B, Xb, Xbt);
+    hipLaunchKernelGGL(gather_batch_kernel, dim3((B + 3) / 4), dim3(256), 0, st, Y, m, p, pairs,
+                       B, Xb, Xbt);
     prof_end(DL_K_MLP, st);
     return hipGetLastError();
 }
 
 hipError_t launch_gather_rows(const float *X, int rows, int cols, uint16_t *Xb, hipStream_t st)
 {
-    const size_t count = (size_t)rows * cols;
     prof_begin(DL_K_MLP, st);
-    hipLaunchKernelGGL(gather_rows_kernel, dim3(grid1(count, 4096)), dim3(256), 0, st, X, count,
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, X, rows, cols,
                        Xb);
     prof_end(DL_K_MLP, st);
     return hipGetLastError();
@@ -322,11 +348,11 @@ hipError_t launch_gather_rows(const float *X, int rows, int cols, uint16_t *Xb, 
 
 hipError_t launch_bce(const float *Z, int out_dim, const int32_t *hist, int s,
                       const int32_t *pairs, int B, uint16_t *dZ, uint16_t *dZt, double *loss_rows,
-                      hipStream_t st)
+                      float w_pos, hipStream_t st)
 {
     prof_begin(DL_K_MLP, st);
     hipLaunchKernelGGL(bce_kernel, dim3((B + 3) / 4), dim3(256), 0, st, Z, out_dim, hist, s,
-                       pairs, B, dZ, dZt, loss_rows);
+                       pairs, B, dZ, dZt, loss_rows, w_pos);
     prof_end(DL_K_MLP, st);
     return hipGetLastError();
 }

@@ -26,7 +26,7 @@ bool mlp_valid(const dl_mlp_params *q)
     return q && q->in_dim >= 8 && q->in_dim % 8 == 0 && q->hidden >= 32 && q->hidden % 32 == 0 &&
            q->out_dim >= 1 && q->out_dim % 8 == 0 && q->batch >= 32 && q->batch % 32 == 0 &&
            q->lr > 0.f && q->beta1 >= 0.f && q->beta1 < 1.f && q->beta2 >= 0.f &&
-           q->beta2 < 1.f && q->eps > 0.f;
+           q->beta2 < 1.f && q->eps > 0.f && q->pos_weight > 0.f;
 }
 
 MlpLayout mlp_layout(const dl_mlp_params &q)
@@ -248,7 +248,7 @@ dl_status dl_mlp_train_step(const dl_mlp_params *q, void *ws, size_t ws_bytes, c
     if (rc != DL_OK)
         return rc;
     MLP_TRY(launch_bce(w.at<float>(L.Z), O, hist, s, pairs, B, w.at<uint16_t>(L.dZ),
-                       w.at<uint16_t>(L.dZt), w.at<double>(L.loss), st));
+                       w.at<uint16_t>(L.dZt), w.at<double>(L.loss), q->pos_weight, st));
     float *gr = w.at<float>(L.grads);
     // layer 3
     rc = weight_grad(*q, w, w.at<uint16_t>(L.dZt), w.at<uint16_t>(L.H2t), O, H, gr + L.oW3, st);

@@ -146,11 +146,12 @@ __global__ __launch_bounds__(64 * kWaves) void omp_kernel(OmpArgs a)
     const int wave = threadIdx.x >> 6;
     const int grp = lane / LPS;   // signal slot of this lane in the wave
     const int l = lane % LPS;     // lane within the group
+    const int m_eff = a.m_dev ? min(*a.m_dev, a.m) : a.m;
     const int wave_sig0 = (blockIdx.x * kWaves + wave) * GPW;
-    if (wave_sig0 >= a.m)
+    if (wave_sig0 >= m_eff)
         return;  // whole wave leaves together; no workgroup barrier follows
     const int i = wave_sig0 + grp;
-    const bool valid = i < a.m;
+    const bool valid = i < m_eff;
     const int n = a.n, p = a.p, s = a.s, ldn = a.ldn;
 
     // ||y|| for the orthogonality stop rule
@@ -349,25 +350,33 @@ __global__ __launch_bounds__(64 * kWaves) void omp_kernel(OmpArgs a)
         if (l == r)
             xown = xs[r];
     }
-    if (!valid)
-        return;
-    if (l < s) {
+    // output row of this signal
+    const int io = (valid && a.rowmap) ? a.rowmap[i] : i;
+    if (valid && l < s) {
         const bool on = l < kg;
-        a.idx[(size_t)i * s + l] = on ? selj : -1;
-        a.val[(size_t)i * s + l] = on ? xown : 0.f;
+        a.idx[(size_t)io * s + l] = on ? selj : -1;
+        a.val[(size_t)io * s + l] = on ? xown : 0.f;
     }
     // residual e = y - D_I x with the dictionary used for coding
-    if (a.E) {
-        for (int q = 4 * l; q < p; q += 4 * LPS) {
-            f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
+    if (a.E || a.rnorm) {
+        float esq = 0.f;
+        if (valid)
+            for (int q = 4 * l; q < p; q += 4 * LPS) {
+                f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
 #pragma unroll
-            for (int t = 0; t < SMAX; ++t)
-                if (t < kg) {
-                    const f32x4 d = *reinterpret_cast<const f32x4 *>(a.D + (size_t)js[t] * p + q);
-                    e -= d * xs[t];
-                }
-            *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e;
-        }
+                for (int t = 0; t < SMAX; ++t)
+                    if (t < kg) {
+                        const f32x4 d =
+                            *reinterpret_cast<const f32x4 *>(a.D + (size_t)js[t] * p + q);
+                        e -= d * xs[t];
+                    }
+                if (a.E)
+                    *reinterpret_cast<f32x4 *>(a.E + (size_t)io * p + q) = e;
+                esq += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + e[3] * e[3];
+            }
+        esq = group_sum<LPS>(esq);
+        if (a.rnorm && valid && l == 0)
+            a.rnorm[io] = sqrtf(esq);
     }
 }
 

@@ -72,6 +72,13 @@ SIGNATURES = {
     "dl_iterate": (ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp]),
     "dl_read_stats": (ctypes.c_int, [_PP, _vp, ctypes.c_size_t, ctypes.POINTER(Stats), _vp]),
+    "dl_iterate_record": (ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         ctypes.c_size_t, _vp]),
+    "dl_proposal_workspace_size": (ctypes.c_size_t, [_PP]),
+    "dl_code_proposed": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                        _vp, ctypes.c_size_t, _vp]),
+    "dl_iterate_proposed": (ctypes.c_int, [_PP, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                           _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp]),
     "dl_mlp_param_count": (ctypes.c_size_t, [ctypes.c_void_p]),
     "dl_mlp_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
     "dl_mlp_init": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -214,7 +221,8 @@ def iterate(prm: Params, Y, D, iters, X_idx, X_val, rmse_out, ws, stream=None):
 class _MlpParams(ctypes.Structure):
     _fields_ = [("in_dim", ctypes.c_int), ("hidden", ctypes.c_int), ("out_dim", ctypes.c_int),
                 ("batch", ctypes.c_int), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
-                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("pos_weight", ctypes.c_float)]
 
 
 @dataclass
@@ -223,14 +231,15 @@ class MlpParams:
     hidden: int
     out_dim: int
     batch: int = 4096
-    lr: float = 1e-3
+    lr: float = 3e-3
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-8
+    pos_weight: float = 1.0
 
     def ref(self):
         self._c = _MlpParams(self.in_dim, self.hidden, self.out_dim, self.batch, self.lr,
-                             self.beta1, self.beta2, self.eps)
+                             self.beta1, self.beta2, self.eps, self.pos_weight)
         return ctypes.cast(ctypes.pointer(self._c), ctypes.c_void_p)
 
 
@@ -288,6 +297,41 @@ def profile_read() -> dict:
     cnt = (ctypes.c_longlong * k)()
     _check(lib().dl_profile_read(ms, cnt, k), "dl_profile_read")
     return {KERNELS[i]: (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+
+def iterate_record(prm: Params, Y, D, iters, X_idx, X_val, rmse_out, hist, rref, ws, stream=None):
+    _check(lib().dl_iterate_record(prm.ref(), _ptr(Y), _ptr(D), int(iters), _ptr(X_idx),
+                                   _ptr(X_val), _ptr(rmse_out), _ptr(hist), _ptr(rref), _ptr(ws),
+                                   ws.numel(), _stream(stream)), "dl_iterate_record")
+
+
+class _Proposal(ctypes.Structure):
+    _fields_ = [("cand", ctypes.c_void_p), ("k", ctypes.c_int), ("margin", ctypes.c_float),
+                ("audit_every", ctypes.c_int)]
+
+
+def proposal_workspace(prm: Params, device="cuda") -> torch.Tensor:
+    n = lib().dl_proposal_workspace_size(prm.ref())
+    if n == 0:
+        raise DLError(DL_EINVAL, "dl_proposal_workspace_size")
+    return torch.empty(int(n), dtype=torch.uint8, device=device)
+
+
+def code_proposed(prm: Params, cand, margin, D, Y, rref, X_idx, X_val, ws, pws, stream=None):
+    pr = _Proposal(ctypes.c_void_p(cand.data_ptr()), cand.shape[1], float(margin), 0)
+    _check(lib().dl_code_proposed(prm.ref(), ctypes.cast(ctypes.pointer(pr), ctypes.c_void_p),
+                                  _ptr(D), _ptr(Y), _ptr(rref), _ptr(X_idx), _ptr(X_val), _ptr(ws),
+                                  ws.numel(), _ptr(pws), pws.numel(), _stream(stream)),
+           "dl_code_proposed")
+
+
+def iterate_proposed(prm: Params, cand, margin, audit_every, Y, D, iters, rref, X_idx, X_val,
+                     rmse_out, ws, pws, stream=None):
+    pr = _Proposal(ctypes.c_void_p(cand.data_ptr()), cand.shape[1], float(margin), int(audit_every))
+    _check(lib().dl_iterate_proposed(prm.ref(), ctypes.cast(ctypes.pointer(pr), ctypes.c_void_p),
+                                     _ptr(Y), _ptr(D), int(iters), _ptr(rref), _ptr(X_idx),
+                                     _ptr(X_val), _ptr(rmse_out), _ptr(ws), ws.numel(), _ptr(pws),
+                                     pws.numel(), _stream(stream)), "dl_iterate_proposed")
 
 
 def read_stats(prm: Params, ws, stream=None, allow_nonfinite=False) -> dict:

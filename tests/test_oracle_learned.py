@@ -4,6 +4,7 @@ backward elimination, brute force over candidate subsets, top-k order."""
 import itertools
 
 import numpy as np
+import pytest
 
 from oracle import learned
 
@@ -13,13 +14,14 @@ def _small_params(rng, sizes=(6, 9, 7, 5)):
             for i, o in zip(sizes[:-1], sizes[1:])]
 
 
-def test_mlp_gradients_match_central_differences():
+@pytest.mark.parametrize("pos_weight", [1.0, 3.5])
+def test_mlp_gradients_match_central_differences(pos_weight):
     rng = np.random.default_rng(0)
     params = _small_params(rng)
     X = rng.standard_normal((11, 6))
     T = (rng.random((11, 5)) < 0.3).astype(float)
     A, Z = learned.forward(params, X)
-    grads = learned.backward(params, A, Z, T)
+    grads = learned.backward(params, A, Z, T, pos_weight)
     h = 1e-6
     for li, (W, b) in enumerate(params):
         for arr, g in ((W, grads[li][0]), (b, grads[li][1])):
@@ -29,9 +31,9 @@ def test_mlp_gradients_match_central_differences():
                 ix = it.multi_index
                 old = arr[ix]
                 arr[ix] = old + h
-                lp = learned.bce_loss(learned.forward(params, X)[1], T)
+                lp = learned.bce_loss(learned.forward(params, X)[1], T, pos_weight)
                 arr[ix] = old - h
-                lm = learned.bce_loss(learned.forward(params, X)[1], T)
+                lm = learned.bce_loss(learned.forward(params, X)[1], T, pos_weight)
                 arr[ix] = old
                 num[ix] = (lp - lm) / (2 * h)
             rel = np.linalg.norm(num - g) / max(np.linalg.norm(num), 1e-12)
@@ -41,9 +43,17 @@ def test_mlp_gradients_match_central_differences():
 def test_bce_loss_closed_forms():
     Z = np.array([[0.0, 2.0], [-3.0, 1.5]])
     T = np.array([[1.0, 0.0], [0.0, 1.0]])
-    want = np.mean([np.log(2), np.log1p(np.exp(2.0)), np.log1p(np.exp(-3.0)),
-                    np.log1p(np.exp(-1.5))])
-    assert abs(learned.bce_loss(Z, T) - want) < 1e-12
+    # -log sigmoid(z) for positives, -log(1 - sigmoid(z)) for negatives
+    terms = [np.log(2), np.log1p(np.exp(2.0)), np.log1p(np.exp(-3.0)), np.log1p(np.exp(-1.5))]
+    assert abs(learned.bce_loss(Z, T) - np.mean(terms)) < 1e-12
+    w = 4.0
+    weighted = [w * terms[0], terms[1], terms[2], w * terms[3]]
+    assert abs(learned.bce_loss(Z, T, w) - np.mean(weighted)) < 1e-12
+
+
+def test_network_input_is_unit_norm_direction():
+    Y = np.array([[3.0, 4.0], [0.0, 0.0]])
+    np.testing.assert_allclose(learned.network_input(Y), [[0.6, 0.8], [0.0, 0.0]])
 
 
 def test_adam_first_step_is_signed_learning_rate():
