@@ -290,6 +290,47 @@ dl_status dl_iterate_proposed(const dl_params *prm, const dl_proposal *pr, const
                               double *rmse, void *ws, size_t ws_bytes, void *pws, size_t pws_bytes,
                               dl_stream_t stream);
 
+/* ---- batched independent problems -----------------------------------------
+   Many independent problems of uneven (p, n, m, s) iterate together (the DL
+   iteration of Alg. 1 with all atoms in one Jacobi group, eq. 2).  Every
+   stage of an iteration is one persistent launch over all problems: its
+   workgroups take (problem, tile) items from a device queue, larger problems
+   first; OMP runs one such launch per lane-group shape in use.  Each problem
+   gets bit-for-bit the results of dl_iterate with the same parameters. */
+typedef struct dl_problem {
+    dl_params prm;    /* FP32 and group_size >= n only; rule, tolerances and OMP
+                         launch shape as for dl_iterate */
+    const float *Y;   /* [m][p] signals (device, 16-byte aligned) */
+    float *D;         /* [n][p] initial dictionary in, learned dictionary out
+                         (rows are normalised first; device, 16-byte aligned) */
+    int32_t *X_idx;   /* [m][s] out: atoms of the last coding (device) */
+    float *X_val;     /* [m][s] out: coefficients after the last update (device) */
+    double *rmse;     /* [iters] out: ||Y - D X||_F / sqrt(p m) after every
+                         iteration (device, 8-byte aligned) */
+} dl_problem;
+
+/* Workspace bytes for the problems (host only; 0 if any is invalid or
+   count is outside 1..4096). */
+size_t dl_batch_workspace_size(const dl_problem *probs, int count);
+
+/* `iters` iterations of every problem.  The workspace (device, 256-byte
+   aligned, dl_batch_workspace_size bytes) needs no initialisation; the call
+   copies its launch tables from host memory and synchronises `stream` once
+   before enqueuing the iterations.  Problems must not share output buffers.
+   DL_EINVAL for a bad problem, size or pointer (nothing is enqueued). */
+dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void *ws,
+                             size_t ws_bytes, dl_stream_t stream);
+
+/* Autotuner of the OMP launch shape: for every distinct (p, n, s) it times
+   each valid (omp_lanes_per_signal, omp_atoms_per_lane) on the largest such
+   problem (its first 16384 signals, correlations from its current D, `reps`
+   timed launches after one warm-up, 1 <= reps <= 1000) and writes the
+   fastest into prm of every problem with that (p, n, s).  Synchronous;
+   overwrites X_idx and X_val of the problems it times, not D.  Workspace as
+   for dl_iterate_batched. */
+dl_status dl_autotune(dl_problem *probs, int count, int reps, void *ws, size_t ws_bytes,
+                      dl_stream_t stream);
+
 /* Synchronise `stream` and copy the workspace counters to *out (host).
    Returns DL_ENUMERIC if any non-finite value was counted, else DL_OK. */
 dl_status dl_read_stats(const dl_params *prm, const void *ws, size_t ws_bytes, dl_stats *out,

@@ -89,6 +89,12 @@ bool valid_params(const dl_params *prm)
 
 bool aligned(const void *ptr, size_t a) { return ptr && ((uintptr_t)ptr % a) == 0; }
 
+}  // namespace
+
+bool dlk::params_ok(const dl_params *prm) { return valid_params(prm); }
+
+namespace {
+
 struct Ws {
     char *base;
     Layout L;

@@ -28,17 +28,16 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(kCsrBlock) void csr_count_kernel(const int32_t *__restrict__ idx,
-                                                              int32_t *__restrict__ blkcnt,
-                                                              int32_t *__restrict__ lrank, int n,
-                                                              int m, int s, int nb)
+// Signal block b of the count pass; smem holds kWavesPerBlock * n 64-bit
+// masks and as many counters.
+__device__ inline void csr_count_body(const int32_t *__restrict__ idx, int32_t *__restrict__ blkcnt,
+                                      int32_t *__restrict__ lrank, int n, int m, int s, int nb,
+                                      int b, unsigned long long *smem)
 {
-    extern __shared__ unsigned long long smem[];
     unsigned long long *masks = smem;                                  // [waves][n]
     int32_t *wcnt = reinterpret_cast<int32_t *>(smem + kWavesPerBlock * n);  // [waves][n]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int b = blockIdx.x;
     for (int t = threadIdx.x; t < kWavesPerBlock * n; t += blockDim.x) {
         masks[t] = 0ull;
         wcnt[t] = 0;
@@ -98,6 +97,15 @@ __global__ __launch_bounds__(kCsrBlock) void csr_count_kernel(const int32_t *__r
     }
 }
 
+__global__ __launch_bounds__(kCsrBlock) void csr_count_kernel(const int32_t *__restrict__ idx,
+                                                              int32_t *__restrict__ blkcnt,
+                                                              int32_t *__restrict__ lrank, int n,
+                                                              int m, int s, int nb)
+{
+    extern __shared__ unsigned long long smem[];
+    csr_count_body(idx, blkcnt, lrank, n, m, s, nb, blockIdx.x, smem);
+}
+
 __device__ inline int wave_inclusive_scan(int x)
 {
     const int lane = threadIdx.x & 63;
@@ -112,17 +120,17 @@ __device__ inline int wave_inclusive_scan(int x)
 
 // Per atom: per-block counts -> offsets inside the atom's user list, and the
 // atom total.  The last workgroup scans the totals into row_ptr / chunk_ptr.
-__global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blkcnt,
-                                                       int32_t *__restrict__ tot,
-                                                       int32_t *__restrict__ row_ptr,
-                                                       int32_t *__restrict__ chunk_ptr,
-                                                       Control *ctl, int n, int nb)
+// Item blk (atoms 4 blk .. 4 blk + 3) of nblk items of the scan.
+__device__ inline void csr_scan_body(int32_t *__restrict__ blkcnt, int32_t *__restrict__ tot,
+                                     int32_t *__restrict__ row_ptr,
+                                     int32_t *__restrict__ chunk_ptr, Control *ctl, int n, int nb,
+                                     int blk, int nblk)
 {
     __shared__ int sh[2][4];
     __shared__ bool am_last;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int a = blockIdx.x * 4 + wave;
+    const int a = blk * 4 + wave;
     if (a < n) {
         int carry = 0;
         for (int b0 = 0; b0 < nb; b0 += 64) {
@@ -140,7 +148,7 @@ __global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blk
     if (threadIdx.x == 0) {
         __threadfence();
         const unsigned prev = atomicAdd(&ctl->csr_done, 1u);
-        am_last = prev == gridDim.x - 1;
+        am_last = prev == (unsigned)nblk - 1;
     }
     __syncthreads();
     if (!am_last)
@@ -192,15 +200,25 @@ __global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blk
     }
 }
 
-__global__ void csr_scatter_kernel(const int32_t *__restrict__ idx,
-                                   const int32_t *__restrict__ blkoff,
-                                   const int32_t *__restrict__ row_ptr,
-                                   const int32_t *__restrict__ lrank, int32_t *__restrict__ users,
-                                   float *__restrict__ val_pad, int n, int m, int s, int nb)
+__global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blkcnt,
+                                                       int32_t *__restrict__ tot,
+                                                       int32_t *__restrict__ row_ptr,
+                                                       int32_t *__restrict__ chunk_ptr,
+                                                       Control *ctl, int n, int nb)
+{
+    csr_scan_body(blkcnt, tot, row_ptr, chunk_ptr, ctl, n, nb, blockIdx.x, gridDim.x);
+}
+
+__device__ inline void csr_scatter_body(const int32_t *__restrict__ idx,
+                                        const int32_t *__restrict__ blkoff,
+                                        const int32_t *__restrict__ row_ptr,
+                                        const int32_t *__restrict__ lrank,
+                                        int32_t *__restrict__ users, float *__restrict__ val_pad,
+                                        int n, int m, int s, int nb, int blk, int nblk)
 {
     const size_t total = (size_t)m * s;
-    for (size_t pos = (size_t)blockIdx.x * blockDim.x + threadIdx.x; pos < total;
-         pos += (size_t)gridDim.x * blockDim.x) {
+    for (size_t pos = (size_t)blk * blockDim.x + threadIdx.x; pos < total;
+         pos += (size_t)nblk * blockDim.x) {
         const int atom = idx[pos];
         if (atom < 0 || atom >= n) {
             if (val_pad)
@@ -212,9 +230,104 @@ __global__ void csr_scatter_kernel(const int32_t *__restrict__ idx,
     }
 }
 
+__global__ void csr_scatter_kernel(const int32_t *__restrict__ idx,
+                                   const int32_t *__restrict__ blkoff,
+                                   const int32_t *__restrict__ row_ptr,
+                                   const int32_t *__restrict__ lrank, int32_t *__restrict__ users,
+                                   float *__restrict__ val_pad, int n, int m, int s, int nb)
+{
+    csr_scatter_body(idx, blkoff, row_ptr, lrank, users, val_pad, n, m, s, nb, blockIdx.x,
+                     gridDim.x);
+}
+
+// ---- batched problems: one launch per pass over every problem's items ----
+__device__ inline int csr_nb(int m) { return (m + kCsrBlock - 1) / kCsrBlock; }
+
+__global__ __launch_bounds__(kCsrBlock) void csr_count_batched(const CsrArgs *__restrict__ tab,
+                                                               BatchList bl)
+{
+    extern __shared__ unsigned long long smem[];
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        const CsrArgs a = tab[b];
+        csr_count_body(a.idx, a.blkcnt, a.lrank, a.n, a.m, a.s, csr_nb(a.m), it - bl.start[b],
+                       smem);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void csr_scan_batched(const CsrArgs *__restrict__ tab,
+                                                        BatchList bl)
+{
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        const CsrArgs a = tab[b];
+        csr_scan_body(a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.ctl, a.n, csr_nb(a.m),
+                      it - bl.start[b], bl.start[b + 1] - bl.start[b]);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void csr_scatter_batched(const CsrArgs *__restrict__ tab,
+                                                           BatchList bl)
+{
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        const CsrArgs a = tab[b];
+        csr_scatter_body(a.idx, a.blkcnt, a.row_ptr, a.lrank, a.users, a.val_pad, a.n, a.m, a.s,
+                         csr_nb(a.m), it - bl.start[b], bl.start[b + 1] - bl.start[b]);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
+}
+
 }  // namespace
 
 int csr_blocks(int m) { return (m + kCsrBlock - 1) / kCsrBlock; }
+
+// Items: count = signal blocks, scan = atom quads, scatter = blocks of 256 entries.
+hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, int count_items,
+                              const BatchList &scan_list, int scan_items,
+                              const BatchList &scatter_list, int scatter_items, int max_n,
+                              hipStream_t st)
+{
+    const size_t shmem = (sizeof(unsigned long long) + sizeof(int32_t)) * kWavesPerBlock * max_n;
+    int wg = batch_workers((const void *)csr_count_batched, kCsrBlock, shmem, count_items);
+    prof_begin(DL_K_CSR_COUNT, st);
+    hipLaunchKernelGGL(csr_count_batched, dim3(wg), dim3(kCsrBlock), shmem, st, tab, count_list);
+    prof_end(DL_K_CSR_COUNT, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    wg = batch_workers((const void *)csr_scan_batched, 256, 0, scan_items);
+    prof_begin(DL_K_CSR_SCAN, st);
+    hipLaunchKernelGGL(csr_scan_batched, dim3(wg), dim3(256), 0, st, tab, scan_list);
+    prof_end(DL_K_CSR_SCAN, st);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    wg = batch_workers((const void *)csr_scatter_batched, 256, 0, scatter_items);
+    prof_begin(DL_K_CSR_SCATTER, st);
+    hipLaunchKernelGGL(csr_scatter_batched, dim3(wg), dim3(256), 0, st, tab, scatter_list);
+    prof_end(DL_K_CSR_SCATTER, st);
+    return hipGetLastError();
+}
 
 hipError_t launch_csr(const CsrArgs &a, hipStream_t st)
 {

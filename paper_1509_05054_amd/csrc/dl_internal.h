@@ -54,6 +54,7 @@ struct Layout {
 };
 
 Layout layout_for(const dl_params &prm);
+bool params_ok(const dl_params *prm);
 int csr_blocks(int m);
 int max_chunks(const dl_params &prm);
 int rmse_blocks(int m);
@@ -209,5 +210,89 @@ struct ProposeArgs {
 hipError_t launch_ls_prune(const ProposeArgs &a, int k2, hipStream_t st);
 hipError_t launch_gather_list(const float *src, int p, const int32_t *list, const int32_t *count,
                               int cap, float *rows, hipStream_t st);
+
+// ---- batched problems (batch_api.hip) ---------------------------------------
+// A batched launch runs one stage for many independent problems.  Problem b
+// owns the work items [start[b], start[b+1]) of the launch; persistent
+// workgroups (or, for OMP, waves) take items from a device ticket counter
+// until none are left.  The last worker to leave resets the counters, so one
+// queue serves every launch of a stream in turn.
+struct BatchQueue {
+    unsigned int ticket;
+    unsigned int exited;
+    unsigned int pad[62];
+};
+struct BatchList {
+    const int32_t *start;  // [count + 1] item prefix sums
+    int count;
+    BatchQueue *q;
+};
+
+// Problem owning item `it` (start is non-decreasing, start[0] = 0).
+__device__ inline int batch_find(const int32_t *start, int count, int it)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= it)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Workgroup-wide: the next item of a batched launch (every thread gets it);
+// `slot` is a shared int of the calling kernel.
+__device__ inline int batch_next_item(BatchQueue *q, int *slot)
+{
+    __syncthreads();  // everyone has read the previous item
+    if (threadIdx.x == 0)
+        *slot = (int)atomicAdd(&q->ticket, 1u);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*slot);
+}
+
+// Called once by every worker after its last item; `workers` is the number
+// of workers in the launch.
+__device__ inline void batch_leave(BatchQueue *q, unsigned workers)
+{
+    __threadfence();
+    const unsigned prev = atomicAdd(&q->exited, 1u);
+    if (prev == workers - 1) {
+        atomicExch(&q->ticket, 0u);
+        atomicExch(&q->exited, 0u);
+    }
+}
+
+struct NormArgs {
+    float *D;
+    int n, p;
+    Control *ctl;
+};
+// Gram and correlation products of one problem (single-problem tiles).
+struct GemmPair {
+    GemmF32 g, c;
+};
+int batch_workers(const void *kernel, int block, size_t lds, int items);
+int gemm_pair_items(const GemmPair &pp);
+hipError_t launch_batched_gemm(const GemmPair *tab, const BatchList &bl, int items,
+                               hipStream_t st);
+hipError_t launch_batched_omp(const OmpArgs *tab, const BatchList &bl, int items, int lps,
+                              int npl, int smax, hipStream_t st);
+hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, int count_items,
+                              const BatchList &scan_list, int scan_items,
+                              const BatchList &scatter_list, int scatter_items, int max_n,
+                              hipStream_t st);
+hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
+                                 int chunk_items, const BatchList &atom_list, int atom_items,
+                                 hipStream_t st);
+hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items, int k,
+                               hipStream_t st);
+hipError_t launch_batched_normalize(const NormArgs *tab, const BatchList &bl, int items,
+                                    hipStream_t st);
+int omp_smax(int s);
+int omp_default_npl(int n, int s);
+int omp_signals_per_item(int lps);
 
 }  // namespace dlk

@@ -58,12 +58,9 @@ __device__ inline bool pick_problem(const P &p0, const P &p1, int tiles_y0, P &o
     return col0 < out.N && row0 < out.M;
 }
 
-__global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1, int tiles_y0)
+// One kBlockM x kBlockN tile of C at (brow0, bcol0), by a 256-thread workgroup.
+__device__ inline void gemm_f32_tile(const GemmF32 &P, int brow0, int bcol0)
 {
-    GemmF32 P;
-    int brow0, bcol0;
-    if (!pick_problem(p0, p1, tiles_y0, P, brow0, bcol0))
-        return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int row0 = brow0 + (wave >> 1) * 16 * kTM;
@@ -115,6 +112,43 @@ __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1
 #pragma unroll
         for (int b = 0; b < kTN; ++b)
             store_tile(P.C, M, N, P.ldc, row0 + 16 * a, col0 + 16 * b, acc[a][b], lane);
+}
+
+__global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1, int tiles_y0)
+{
+    GemmF32 P;
+    int brow0, bcol0;
+    if (pick_problem(p0, p1, tiles_y0, P, brow0, bcol0))
+        gemm_f32_tile(P, brow0, bcol0);
+}
+
+__host__ __device__ inline int gemm_tiles(const GemmF32 &P)
+{
+    return ((P.M + kBlockM - 1) / kBlockM) * ((P.N + kBlockN - 1) / kBlockN);
+}
+
+// Batched problems: the items of problem b are the tiles of its Gram matrix,
+// then those of its correlations, row-major over the tile grid.
+__global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmPair *__restrict__ tab,
+                                                           BatchList bl)
+{
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        int t = it - bl.start[b];
+        const int tg = gemm_tiles(tab[b].g);
+        const GemmF32 P = t < tg ? tab[b].g : tab[b].c;
+        if (t >= tg)
+            t -= tg;
+        const int tx = (P.N + kBlockN - 1) / kBlockN;
+        gemm_f32_tile(P, (t / tx) * kBlockM, (t % tx) * kBlockN);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
 }
 
 // 8 consecutive BF16 values (K % 4 == 0: a tail of 4 is loaded exactly).
@@ -226,6 +260,18 @@ hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hip
 hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st)
 {
     return launch_grouped(gemm_nt_bf16_kernel, p0, p1, kid, st);
+}
+
+int gemm_pair_items(const GemmPair &pp) { return gemm_tiles(pp.g) + gemm_tiles(pp.c); }
+
+hipError_t launch_batched_gemm(const GemmPair *tab, const BatchList &bl, int items,
+                               hipStream_t st)
+{
+    const int wg = batch_workers((const void *)gemm_batched_kernel, 256, 0, items);
+    prof_begin(DL_K_CORR, st);
+    hipLaunchKernelGGL(gemm_batched_kernel, dim3(wg), dim3(256), 0, st, tab, bl);
+    prof_end(DL_K_CORR, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_cast_bf16(const float *x, uint16_t *y, size_t count, hipStream_t st)

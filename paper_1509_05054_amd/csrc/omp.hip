@@ -17,6 +17,10 @@ static int smax_for(int s)
     return s <= 4 ? 4 : s <= 6 ? 6 : s <= 8 ? 8 : s <= 12 ? 12 : 16;
 }
 
+int omp_smax(int s) { return smax_for(s); }
+
+int omp_signals_per_item(int lps) { return 64 / lps; }
+
 // Default lanes per signal for n atoms at `npl` atoms per lane: enough lanes
 // for the atoms and one lane per row of the Cholesky factor.
 int omp_lanes_per_signal(int n, int npl, int s)
@@ -37,16 +41,32 @@ bool omp_config_ok(int n, int s, int lps, int npl)
     return lps_ok && npl_ok && lps * npl >= n && lps >= smax_for(s);
 }
 
+// 16 correlations per lane, fewer when the group must be wide for L anyway.
+int omp_default_npl(int n, int s)
+{
+    int npl = 16;
+    while (npl > 4 && omp_lanes_per_signal(n, npl, s) * (npl / 2) >= n &&
+           omp_lanes_per_signal(n, npl / 2, s) == omp_lanes_per_signal(n, npl, s))
+        npl /= 2;
+    return npl;
+}
+
+hipError_t launch_batched_omp(const OmpArgs *tab, const BatchList &bl, int items, int lps,
+                              int npl, int smax, hipStream_t st)
+{
+    switch (npl) {
+    case 4: return launch_omp_batched_npl4(tab, bl, items, lps, smax, st);
+    case 8: return launch_omp_batched_npl8(tab, bl, items, lps, smax, st);
+    case 16: return launch_omp_batched_npl16(tab, bl, items, lps, smax, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_omp(const OmpArgs &a, hipStream_t st)
 {
     int npl = a.atoms_per_lane;
-    if (npl <= 0) {
-        // 16 correlations per lane, fewer when the group must be wide for L
-        npl = 16;
-        while (npl > 4 && omp_lanes_per_signal(a.n, npl, a.s) * (npl / 2) >= a.n &&
-               omp_lanes_per_signal(a.n, npl / 2, a.s) == omp_lanes_per_signal(a.n, npl, a.s))
-            npl /= 2;
-    }
+    if (npl <= 0)
+        npl = omp_default_npl(a.n, a.s);
     const int lps = a.lanes_per_signal > 0 ? a.lanes_per_signal
                                            : omp_lanes_per_signal(a.n, npl, a.s);
     if (!omp_config_ok(a.n, a.s, lps, npl))

@@ -130,8 +130,10 @@ __device__ inline void load_row(vec_t<NPL> &v, const float *row, int first, int 
     }
 }
 
+// The GPW = 64 / LPS signals [wave_sig0, wave_sig0 + GPW) of one wave
+// (signals at or beyond m_eff are skipped); waves never wait for each other.
 template <int LPS, int NPL, int SMAX>
-__global__ __launch_bounds__(64 * kWaves) void omp_kernel(OmpArgs a)
+__device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int m_eff)
 {
     static_assert(LPS >= SMAX, "one lane per row of L");
     constexpr int GPW = 64 / LPS;                 // signals per wave
@@ -146,10 +148,6 @@ __global__ __launch_bounds__(64 * kWaves) void omp_kernel(OmpArgs a)
     const int wave = threadIdx.x >> 6;
     const int grp = lane / LPS;   // signal slot of this lane in the wave
     const int l = lane % LPS;     // lane within the group
-    const int m_eff = a.m_dev ? min(*a.m_dev, a.m) : a.m;
-    const int wave_sig0 = (blockIdx.x * kWaves + wave) * GPW;
-    if (wave_sig0 >= m_eff)
-        return;  // whole wave leaves together; no workgroup barrier follows
     const int i = wave_sig0 + grp;
     const bool valid = i < m_eff;
     const int n = a.n, p = a.p, s = a.s, ldn = a.ldn;
@@ -381,6 +379,54 @@ __global__ __launch_bounds__(64 * kWaves) void omp_kernel(OmpArgs a)
 }
 
 template <int LPS, int NPL, int SMAX>
+__global__ __launch_bounds__(64 * kWaves) void omp_kernel(OmpArgs a)
+{
+    constexpr int GPW = 64 / LPS;
+    const int m_eff = a.m_dev ? min(*a.m_dev, a.m) : a.m;
+    const int wave_sig0 = (blockIdx.x * kWaves + (int)(threadIdx.x >> 6)) * GPW;
+    if (wave_sig0 >= m_eff)
+        return;  // whole wave leaves together; no workgroup barrier follows
+    omp_signals<LPS, NPL, SMAX>(a, wave_sig0, m_eff);
+}
+
+// Batched problems of one launch shape: every wave takes items (GPW signals
+// of one problem) from the queue until none are left.
+template <int LPS, int NPL, int SMAX>
+__global__ __launch_bounds__(64 * kWaves) void omp_batched_kernel(const OmpArgs *__restrict__ tab,
+                                                                  BatchList bl)
+{
+    constexpr int GPW = 64 / LPS;
+    const int lane = threadIdx.x & 63;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        int it = 0;
+        if (lane == 0)
+            it = (int)atomicAdd(&bl.q->ticket, 1u);
+        it = __builtin_amdgcn_readfirstlane(it);  // lane 0's ticket, wave-uniform
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        const OmpArgs a = tab[b];
+        omp_signals<LPS, NPL, SMAX>(a, (it - bl.start[b]) * GPW, a.m);
+    }
+    if (lane == 0)
+        batch_leave(bl.q, gridDim.x * kWaves);
+}
+
+template <int LPS, int NPL, int SMAX>
+hipError_t launch_omp_batched_t(const OmpArgs *tab, const BatchList &bl, int items,
+                                hipStream_t st)
+{
+    const int wg = batch_workers((const void *)omp_batched_kernel<LPS, NPL, SMAX>, 64 * kWaves, 0,
+                                 (items + kWaves - 1) / kWaves);
+    prof_begin(DL_K_OMP, st);
+    hipLaunchKernelGGL((omp_batched_kernel<LPS, NPL, SMAX>), dim3(wg), dim3(64 * kWaves), 0, st,
+                       tab, bl);
+    prof_end(DL_K_OMP, st);
+    return hipGetLastError();
+}
+
+template <int LPS, int NPL, int SMAX>
 hipError_t launch_omp_t(const OmpArgs &a, hipStream_t st)
 {
     constexpr int sig_per_block = kWaves * (64 / LPS);
@@ -389,6 +435,27 @@ hipError_t launch_omp_t(const OmpArgs &a, hipStream_t st)
     hipLaunchKernelGGL((omp_kernel<LPS, NPL, SMAX>), dim3(blocks), dim3(64 * kWaves), 0, st, a);
     prof_end(DL_K_OMP, st);
     return hipGetLastError();
+}
+
+template <int LPS, int NPL>
+hipError_t launch_omp_batched_s(const OmpArgs *tab, const BatchList &bl, int items, int smax,
+                                hipStream_t st)
+{
+    if (smax == 4)
+        return launch_omp_batched_t<LPS, NPL, 4>(tab, bl, items, st);
+    if constexpr (LPS >= 8) {
+        if (smax == 6)
+            return launch_omp_batched_t<LPS, NPL, 6>(tab, bl, items, st);
+        if (smax == 8)
+            return launch_omp_batched_t<LPS, NPL, 8>(tab, bl, items, st);
+    }
+    if constexpr (LPS >= 16) {
+        if (smax == 12)
+            return launch_omp_batched_t<LPS, NPL, 12>(tab, bl, items, st);
+        if (smax == 16)
+            return launch_omp_batched_t<LPS, NPL, 16>(tab, bl, items, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 // Dispatch over SMAX for one (LPS, NPL); configurations with LPS < SMAX are
@@ -417,5 +484,11 @@ hipError_t launch_omp_s(const OmpArgs &a, hipStream_t st)
 hipError_t launch_omp_npl4(const OmpArgs &a, int lps, hipStream_t st);
 hipError_t launch_omp_npl8(const OmpArgs &a, int lps, hipStream_t st);
 hipError_t launch_omp_npl16(const OmpArgs &a, int lps, hipStream_t st);
+hipError_t launch_omp_batched_npl4(const OmpArgs *tab, const BatchList &bl, int items, int lps,
+                                   int smax, hipStream_t st);
+hipError_t launch_omp_batched_npl8(const OmpArgs *tab, const BatchList &bl, int items, int lps,
+                                   int smax, hipStream_t st);
+hipError_t launch_omp_batched_npl16(const OmpArgs *tab, const BatchList &bl, int items, int lps,
+                                    int smax, hipStream_t st);
 
 }  // namespace dlk

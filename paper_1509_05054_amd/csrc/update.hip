@@ -58,7 +58,7 @@ __device__ inline int chunk_atom(const int32_t *chunk_ptr, int a0, int a1, int g
 // ---- pass 1: partial F x^T per chunk ------------------------------------
 // The chunk's ELL positions and coefficients are staged in LDS first, so the
 // residual rows of several users are in flight at once.
-__global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1)
+__device__ inline void pass1_body(const UpdateArgs &a, int a0, int a1, int blk, int nblk)
 {
     __shared__ f32x4 red[4][64];
     __shared__ int sPos[kChunk];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1
     const int q = 4 * (lane % lpu); // first coordinate of this lane
     const int cbase = a.chunk_ptr[a0];
     const int nch = a.chunk_ptr[a1] - cbase;
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+    for (int c = blk; c < nch; c += nblk) {
         const int gc = cbase + c;
         const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
         const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
@@ -108,12 +108,17 @@ __global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1
     }
 }
 
+__global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1)
+{
+    pass1_body(a, a0, a1, blockIdx.x, gridDim.x);
+}
+
 // ---- reduce over chunks + normalise (one wave per atom) -----------------
-__global__ __launch_bounds__(256) void reduce_kernel(UpdateArgs a, int a0, int a1)
+__device__ inline void reduce_body(const UpdateArgs &a, int a0, int a1, int blk)
 {
     const int p = a.p;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = a0 + blockIdx.x * 4 + wave;
+    const int j = a0 + blk * 4 + wave;
     if (j >= a1)
         return;
     const int c0 = a.chunk_ptr[j], c1 = a.chunk_ptr[j + 1];
@@ -158,8 +163,13 @@ __global__ __launch_bounds__(256) void reduce_kernel(UpdateArgs a, int a0, int a
     }
 }
 
+__global__ __launch_bounds__(256) void reduce_kernel(UpdateArgs a, int a0, int a1)
+{
+    reduce_body(a, a0, a1, blockIdx.x);
+}
+
 // ---- pass 2: AK-SVD representation refresh ------------------------------
-__global__ __launch_bounds__(256) void pass2_kernel(UpdateArgs a, int a0, int a1)
+__device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, int nblk)
 {
     __shared__ int sPos[kChunk];
     __shared__ float sX[kChunk];
@@ -171,7 +181,7 @@ __global__ __launch_bounds__(256) void pass2_kernel(UpdateArgs a, int a0, int a1
     const int q = 4 * (lane % lpu);
     const int cbase = a.chunk_ptr[a0];
     const int nch = a.chunk_ptr[a1] - cbase;
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+    for (int c = blk; c < nch; c += nblk) {
         const int gc = cbase + c;
         const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
         const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
@@ -212,6 +222,11 @@ __global__ __launch_bounds__(256) void pass2_kernel(UpdateArgs a, int a0, int a1
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void pass2_kernel(UpdateArgs a, int a0, int a1)
+{
+    pass2_body(a, a0, a1, blockIdx.x, gridDim.x);
 }
 
 // ---- incremental error update after a group (group sizes below n) -------
@@ -265,7 +280,7 @@ __global__ __launch_bounds__(256) void eupdate_kernel(UpdateArgs a, int a0, int 
 // staged in LDS, each lane group forms one residual row at a time, squares
 // are accumulated in FP64; the last workgroup to finish sums the per-block
 // partials in block order.
-__global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
+__device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
 {
     __shared__ double red[256];
     __shared__ int sIdx[kRmseSignals * 16];
@@ -277,7 +292,7 @@ __global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
     const int upw = 64 / lpu;
     const int sub = lane / lpu;
     const int q = 4 * (lane % lpu);
-    const int i0 = blockIdx.x * kRmseSignals;
+    const int i0 = blk * kRmseSignals;
     const int nsig = min(kRmseSignals, a.m - i0);
     for (int r = threadIdx.x; r < nsig * s; r += blockDim.x) {
         sIdx[r] = a.idx[(size_t)i0 * s + r];
@@ -308,17 +323,17 @@ __global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        a.partial[blockIdx.x] = red[0];
+        a.partial[blk] = red[0];
         __threadfence();
         const unsigned prev = atomicAdd(&a.ctl->rmse_done, 1u);
-        am_last = prev == gridDim.x - 1;
+        am_last = prev == (unsigned)nblk - 1;
     }
     __syncthreads();
     if (am_last) {
         __threadfence();
         // fixed-order final sum over the blocks' partials
         double v = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x)
             v += __hip_atomic_load(&a.partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         red[threadIdx.x] = v;
         __syncthreads();
@@ -335,6 +350,11 @@ __global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
             a.ctl->rmse_done = 0;  // ready for the next call
         }
     }
+}
+
+__global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
+{
+    rmse_body(a, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void residual_kernel(const float *__restrict__ Y,
@@ -365,10 +385,10 @@ __global__ __launch_bounds__(256) void residual_kernel(const float *__restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void normalize_kernel(float *D, int n, int p, Control *ctl)
+__device__ inline void normalize_body(float *D, int n, int p, Control *ctl, int blk)
 {
     const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int j = blk * 4 + (threadIdx.x >> 6);
     if (j >= n)
         return;
     float v[4];
@@ -396,6 +416,75 @@ __global__ __launch_bounds__(256) void normalize_kernel(float *D, int n, int p, 
         if (q < p)
             D[(size_t)j * p + q] = v[r] * inv;
     }
+}
+
+__global__ __launch_bounds__(256) void normalize_kernel(float *D, int n, int p, Control *ctl)
+{
+    normalize_body(D, n, p, ctl, blockIdx.x);
+}
+
+// ---- batched problems (one group per problem: atoms [0, n)) --------------
+// Items: pass 1 and pass 2 = chunk slots (an upper bound of the chunks; the
+// excess leaves at once), reduce = atom quads, error = signal blocks,
+// normalisation = atom quads.
+template <int STAGE>
+__global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restrict__ tab,
+                                                      BatchList bl)
+{
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        const UpdateArgs a = tab[b];
+        const int t = it - bl.start[b], nt = bl.start[b + 1] - bl.start[b];
+        if (STAGE == 0)
+            pass1_body(a, 0, a.n, t, nt);
+        else if (STAGE == 1)
+            reduce_body(a, 0, a.n, t);
+        else
+            pass2_body(a, 0, a.n, t, nt);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
+}
+
+// The error of iteration k goes to out[k] of every problem.
+__global__ __launch_bounds__(256) void rmse_batched(const RmseArgs *__restrict__ tab, BatchList bl,
+                                                    int k)
+{
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        RmseArgs a = tab[b];
+        a.out += k;
+        rmse_body(a, it - bl.start[b], bl.start[b + 1] - bl.start[b]);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void normalize_batched(const NormArgs *__restrict__ tab,
+                                                         BatchList bl)
+{
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        const NormArgs a = tab[b];
+        normalize_body(a.D, a.n, a.p, a.ctl, it - bl.start[b]);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
 }
 
 __global__ void copy_kernel(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
@@ -470,6 +559,50 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
         }
     }
     return hipSuccess;
+}
+
+hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
+                                 int chunk_items, const BatchList &atom_list, int atom_items,
+                                 hipStream_t st)
+{
+    int wg = batch_workers((const void *)update_batched<0>, 256, 0, chunk_items);
+    prof_begin(DL_K_UPD_PASS1, st);
+    hipLaunchKernelGGL(update_batched<0>, dim3(wg), dim3(256), 0, st, tab, chunk_list);
+    prof_end(DL_K_UPD_PASS1, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    wg = batch_workers((const void *)update_batched<1>, 256, 0, atom_items);
+    prof_begin(DL_K_UPD_REDUCE, st);
+    hipLaunchKernelGGL(update_batched<1>, dim3(wg), dim3(256), 0, st, tab, atom_list);
+    prof_end(DL_K_UPD_REDUCE, st);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    wg = batch_workers((const void *)update_batched<2>, 256, 0, chunk_items);
+    prof_begin(DL_K_UPD_PASS2, st);
+    hipLaunchKernelGGL(update_batched<2>, dim3(wg), dim3(256), 0, st, tab, chunk_list);
+    prof_end(DL_K_UPD_PASS2, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items, int k,
+                               hipStream_t st)
+{
+    const int wg = batch_workers((const void *)rmse_batched, 256, 0, items);
+    prof_begin(DL_K_RMSE, st);
+    hipLaunchKernelGGL(rmse_batched, dim3(wg), dim3(256), 0, st, tab, bl, k);
+    prof_end(DL_K_RMSE, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_normalize(const NormArgs *tab, const BatchList &bl, int items,
+                                    hipStream_t st)
+{
+    const int wg = batch_workers((const void *)normalize_batched, 256, 0, items);
+    prof_begin(DL_K_MISC, st);
+    hipLaunchKernelGGL(normalize_batched, dim3(wg), dim3(256), 0, st, tab, bl);
+    prof_end(DL_K_MISC, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_rmse(const RmseArgs &a, hipStream_t st)

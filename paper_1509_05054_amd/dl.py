@@ -51,9 +51,16 @@ class Stats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [("prm", _Params), ("Y", ctypes.c_void_p), ("D", ctypes.c_void_p),
+                ("X_idx", ctypes.c_void_p), ("X_val", ctypes.c_void_p),
+                ("rmse", ctypes.c_void_p)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _PP = ctypes.POINTER(_Params)
+_PB = ctypes.POINTER(_Problem)
 
 # name -> (restype, argtypes); the same list is checked against the header by the tests
 SIGNATURES = {
@@ -88,6 +95,10 @@ SIGNATURES = {
                                    ctypes.POINTER(ctypes.c_double), _vp]),
     "dl_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int, _vp, _vp]),
     "dl_topk": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    "dl_batch_workspace_size": (ctypes.c_size_t, [_PB, ctypes.c_int]),
+    "dl_iterate_batched": (ctypes.c_int, [_PB, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t,
+                                          _vp]),
+    "dl_autotune": (ctypes.c_int, [_PB, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "dl_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
@@ -341,3 +352,55 @@ def read_stats(prm: Params, ws, stream=None, allow_nonfinite=False) -> dict:
         return st.as_dict()
     _check(rc, "dl_read_stats")
     return st.as_dict()
+
+
+# ---------------------------------------------------------------- batched problems
+@dataclass
+class Problem:
+    """One problem of a batched call: parameters and its device tensors
+    (Y [m][p], D [n][p] in/out, X_idx/X_val [m][s] out, rmse [iters] float64 out)."""
+    prm: Params
+    Y: torch.Tensor
+    D: torch.Tensor
+    X_idx: torch.Tensor
+    X_val: torch.Tensor
+    rmse: torch.Tensor | None = None
+
+
+def _problem_array(problems):
+    arr = (_Problem * len(problems))()
+    for k, pb in enumerate(problems):
+        arr[k].prm = pb.prm.c()
+        arr[k].Y = _ptr(pb.Y).value if pb.Y is not None else None
+        arr[k].D = _ptr(pb.D).value if pb.D is not None else None
+        arr[k].X_idx = _ptr(pb.X_idx).value if pb.X_idx is not None else None
+        arr[k].X_val = _ptr(pb.X_val).value if pb.X_val is not None else None
+        arr[k].rmse = _ptr(pb.rmse).value if pb.rmse is not None else None
+    return arr
+
+
+def batch_workspace(problems, device="cuda") -> torch.Tensor:
+    n = lib().dl_batch_workspace_size(_problem_array(problems), len(problems))
+    if n == 0:
+        raise DLError(DL_EINVAL, "dl_batch_workspace_size")
+    return torch.empty(int(n), dtype=torch.uint8, device=device)
+
+
+def iterate_batched(problems, iters, ws, stream=None):
+    arr = _problem_array(problems)
+    _check(lib().dl_iterate_batched(arr, len(problems), int(iters), _ptr(ws), ws.numel(),
+                                    _stream(stream)), "dl_iterate_batched")
+
+
+def autotune(problems, ws, reps=3, stream=None):
+    """Time the OMP launch shapes and store the fastest in every problem's
+    ``prm`` (``omp_lanes_per_signal``, ``omp_atoms_per_lane``); returns them."""
+    arr = _problem_array(problems)
+    _check(lib().dl_autotune(arr, len(problems), int(reps), _ptr(ws), ws.numel(),
+                             _stream(stream)), "dl_autotune")
+    out = []
+    for k, pb in enumerate(problems):
+        pb.prm.omp_lanes_per_signal = int(arr[k].prm.omp_lanes_per_signal)
+        pb.prm.omp_atoms_per_lane = int(arr[k].prm.omp_atoms_per_lane)
+        out.append((pb.prm.omp_lanes_per_signal, pb.prm.omp_atoms_per_lane))
+    return out

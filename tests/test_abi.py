@@ -81,3 +81,41 @@ def test_null_and_misaligned_pointers_rejected_before_launch():
     # negative iteration count
     assert L.dl_iterate(prm.ref(), fake, fake, -1, fake, fake, fake, fake, 1 << 30,
                         None) == dl.DL_EINVAL
+
+
+def _fake_problem(**kw):
+    pb = dl._Problem()
+    q = dict(p=16, n=32, m=100, s=3)
+    q.update({k: v for k, v in kw.items() if k in ("p", "n", "m", "s")})
+    pb.prm = dl.Params(**q).c()
+    if "group_size" in kw:
+        pb.prm.group_size = kw["group_size"]
+    if "precision" in kw:
+        pb.prm.precision = kw["precision"]
+    for name in ("Y", "D", "X_idx", "X_val", "rmse"):
+        setattr(pb, name, 0x100000)
+    return pb
+
+
+def test_batched_calls_validate_on_the_host():
+    L = dl.lib()
+    good = (dl._Problem * 2)(_fake_problem(), _fake_problem(p=64, n=256, m=5000, s=6))
+    size = L.dl_batch_workspace_size(good, 2)
+    singles = sum(dl.workspace_size(dl.Params(p, n, m, s))
+                  for p, n, m, s in ((16, 32, 100, 3), (64, 256, 5000, 6)))
+    assert size >= singles
+    assert L.dl_batch_workspace_size(good, 0) == 0
+    for bad in (dict(group_size=8), dict(precision=dl.PREC_BF16), dict(p=6), dict(s=0)):
+        arr = (dl._Problem * 2)(_fake_problem(), _fake_problem(**bad))
+        assert L.dl_batch_workspace_size(arr, 2) == 0, bad
+        assert L.dl_iterate_batched(arr, 2, 1, ctypes.c_void_p(0x1000), 1 << 40, None) \
+            == dl.DL_EINVAL, bad
+    ws = ctypes.c_void_p(0x1000)
+    assert L.dl_iterate_batched(good, 2, 1, ws, 256, None) == dl.DL_EWORKSPACE
+    assert L.dl_iterate_batched(good, 2, -1, ws, 1 << 40, None) == dl.DL_EINVAL
+    assert L.dl_iterate_batched(good, 2, 1, ctypes.c_void_p(0x1010), 1 << 40, None) == dl.DL_EINVAL
+    assert L.dl_autotune(good, 2, 0, ws, 1 << 40, None) == dl.DL_EINVAL
+    assert L.dl_autotune(good, 2, 3, ws, 256, None) == dl.DL_EWORKSPACE
+    misaligned = (dl._Problem * 1)(_fake_problem())
+    misaligned[0].D = 0x100004
+    assert L.dl_iterate_batched(misaligned, 1, 1, ws, 1 << 40, None) == dl.DL_EINVAL
