@@ -264,8 +264,8 @@ typedef struct dl_proposal {
     float margin;         /* hand a signal back to OMP when its residual exceeds
                              (1 + margin) times its reference OMP residual (0.02) */
     int audit_every;      /* code every signal with OMP on every audit_every-th
-                             iteration, refreshing the references (0 = never; the
-                             last iteration is never an audit) */
+                             iteration (iterations audit_every, 2 audit_every, ...
+                             of the call), refreshing the references (0 = never) */
 } dl_proposal;
 
 /* Bytes of the proposal workspace (fallback list and gathered signals). */

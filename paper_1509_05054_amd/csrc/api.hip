@@ -590,7 +590,7 @@ dl_status dl_iterate_proposed(const dl_params *prm, const dl_proposal *pr, const
     float *val_ws = w.at<float>(w.L.val_ws);
     float *Dcur = D, *Dnext = Dws;
     for (int k = 0; k < iters; ++k) {
-        const bool audit = pr->audit_every > 0 && (k + 1) % pr->audit_every == 0 && k + 1 < iters;
+        const bool audit = pr->audit_every > 0 && (k + 1) % pr->audit_every == 0;
         if (audit) {
             OmpExtra x;
             x.rnorm = rref;

@@ -253,3 +253,29 @@ def test_learned_pipeline_gains_over_untrained_network():
     assert r_trained > r_untrained + 0.3
     assert fb_trained < fb_untrained
     assert abs(rl[-1] - rp[-1]) / rp[-1] < 0.05
+
+
+def test_audit_on_every_iteration_is_the_plain_iteration():
+    """An audit codes every signal with OMP, so with one on every iteration
+    the learned iterations reproduce the plain ones bit for bit."""
+    note("learned iterations, audit every iteration")
+    w, D, _, _, cand = _proposal_setup(m=4000)
+    prm = dl.Params(w.p, w.n, w.m, w.s)
+    iters = 3
+    Y = dev(w.Y)
+    out = []
+    for learned_path in (True, False):
+        ws = dl.workspace(prm)
+        Dg = dev(w.D0)
+        idx = torch.empty((w.m, w.s), dtype=torch.int32, device="cuda")
+        val = torch.empty((w.m, w.s), device="cuda")
+        r = torch.empty(iters, dtype=torch.float64, device="cuda")
+        if learned_path:
+            rr = torch.full((w.m,), 1e30, device="cuda")
+            dl.iterate_proposed(prm, dev(cand, torch.int32), 0.02, 1, Y, Dg, iters, rr, idx, val,
+                                r, ws, dl.proposal_workspace(prm))
+        else:
+            dl.iterate(prm, Y, Dg, iters, idx, val, r, ws)
+        out.append([host(t) for t in (Dg, idx, val, r)])
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
