@@ -369,6 +369,11 @@ def main():
                     help="extra configurations to measure (comma list, or 'none')")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the warm-up and timed steps only (for profilers)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 256 MiB read + 256 MiB write elementwise kernel, "
+                         "the reference for scaling HBM counters")
+    ap.add_argument("--row-only", default=None,
+                    help="measure only this row (precision, learned or batched) and print it")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -381,6 +386,18 @@ def main():
     from paper_1509_05054_amd import dl, synth
 
     g = Gpu()
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 2.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+    if args.row_only:
+        fn = {"precision": lambda: row_precision(g, 2), "learned": lambda: row_learned(g),
+              "batched": lambda: row_batched(g, 2)}[args.row_only]
+        print(json.dumps({args.row_only: fn()}))
+        return
     w = synth.workload(args.workload)
     iters = args.iters or w.iters
     gs = args.group_size or w.n
