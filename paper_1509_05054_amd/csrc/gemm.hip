@@ -44,7 +44,7 @@ __device__ inline void store_tile(float *C, int M, int N, int ldc, int row0, int
 // computes, and its tile origin.
 template <class P>
 __device__ inline bool pick_problem(const P &p0, const P &p1, int tiles_y0, P &out, int &row0,
-                                    int &col0)
+                                    int &col0, int block_m = kBlockM)
 {
     const int by = blockIdx.y;
     out = by < tiles_y0 ? p0 : p1;
@@ -53,14 +53,17 @@ __device__ inline bool pick_problem(const P &p0, const P &p1, int tiles_y0, P &o
         out.M = md < out.M ? md : out.M;
     }
     const int ty = by < tiles_y0 ? by : by - tiles_y0;
-    row0 = ty * kBlockM;
+    row0 = ty * block_m;
     col0 = blockIdx.x * kBlockN;
     return col0 < out.N && row0 < out.M;
 }
 
-// One kBlockM x kBlockN tile of C at (brow0, bcol0), by a 256-thread workgroup.
+// One (32 TM) x kBlockN tile of C at (brow0, bcol0), by a 256-thread
+// workgroup; every element is summed in the same K order for any TM.
+template <int TM>
 __device__ inline void gemm_f32_tile(const GemmF32 &P, int brow0, int bcol0)
 {
+    constexpr int kTM = TM;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int row0 = brow0 + (wave >> 1) * 16 * kTM;
@@ -114,17 +117,22 @@ __device__ inline void gemm_f32_tile(const GemmF32 &P, int brow0, int bcol0)
             store_tile(P.C, M, N, P.ldc, row0 + 16 * a, col0 + 16 * b, acc[a][b], lane);
 }
 
+// FP32 products use workgroup tiles of kF32M rows (64: measured faster than
+// 32 on the short-K products, K = p).
+constexpr int kF32TM = 2;
+constexpr int kF32M = 32 * kF32TM;
+
 __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1, int tiles_y0)
 {
     GemmF32 P;
     int brow0, bcol0;
-    if (pick_problem(p0, p1, tiles_y0, P, brow0, bcol0))
-        gemm_f32_tile(P, brow0, bcol0);
+    if (pick_problem(p0, p1, tiles_y0, P, brow0, bcol0, kF32M))
+        gemm_f32_tile<kF32TM>(P, brow0, bcol0);
 }
 
 __host__ __device__ inline int gemm_tiles(const GemmF32 &P)
 {
-    return ((P.M + kBlockM - 1) / kBlockM) * ((P.N + kBlockN - 1) / kBlockN);
+    return ((P.M + kF32M - 1) / kF32M) * ((P.N + kBlockN - 1) / kBlockN);
 }
 
 // Batched problems: the items of problem b are the tiles of its Gram matrix,
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmPair *__res
         if (t >= tg)
             t -= tg;
         const int tx = (P.N + kBlockN - 1) / kBlockN;
-        gemm_f32_tile(P, (t / tx) * kBlockM, (t % tx) * kBlockN);
+        gemm_f32_tile<kF32TM>(P, (t / tx) * kF32M, (t % tx) * kBlockN);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -237,10 +245,11 @@ __global__ void cast_bf16_kernel(const float *__restrict__ x, uint16_t *__restri
 }
 
 template <class P, class Kern>
-hipError_t launch_grouped(Kern kern, const P &p0, const P *p1, int kid, hipStream_t st)
+hipError_t launch_grouped(Kern kern, const P &p0, const P *p1, int kid, hipStream_t st,
+                          int block_m = kBlockM)
 {
-    const int ty0 = (p0.M + kBlockM - 1) / kBlockM;
-    const int ty1 = p1 ? (p1->M + kBlockM - 1) / kBlockM : 0;
+    const int ty0 = (p0.M + block_m - 1) / block_m;
+    const int ty1 = p1 ? (p1->M + block_m - 1) / block_m : 0;
     int tx = (p0.N + kBlockN - 1) / kBlockN;
     if (p1)
         tx = tx > (p1->N + kBlockN - 1) / kBlockN ? tx : (p1->N + kBlockN - 1) / kBlockN;
@@ -254,7 +263,7 @@ hipError_t launch_grouped(Kern kern, const P &p0, const P *p1, int kid, hipStrea
 
 hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st)
 {
-    return launch_grouped(gemm_nt_f32_kernel, p0, p1, kid, st);
+    return launch_grouped(gemm_nt_f32_kernel, p0, p1, kid, st, kF32M);
 }
 
 hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st)

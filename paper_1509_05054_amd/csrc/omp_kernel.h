@@ -175,14 +175,15 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
     vec_t<NPL> u[US];
     float Lrow[SMAX];     // row l of L (this lane's row)
     float cv[SMAX];       // c_t, the same in every lane of the group
-    float dg[SMAX];       // L[t][t]
+    float dgi[SMAX];      // 1 / L[t][t]
+    float rdg = 1.f;      // 1 / L[l][l], this lane's own diagonal
     int js[SMAX];         // selected atoms
     int selj = -1;        // this lane's atom (row l)
 #pragma unroll
     for (int t = 0; t < SMAX; ++t) {
         Lrow[t] = 0.f;
         cv[t] = 0.f;
-        dg[t] = 1.f;
+        dgi[t] = 1.f;
         js[t] = 0;
     }
     bool active = valid && isfinite(ynorm);
@@ -190,9 +191,11 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         atomicAdd(&a.ctl->nonfinite, 1ull);
     int kg = 0;  // atoms selected for this lane's signal
 
-#pragma unroll 1
-    for (int k = 0; k < s; ++k) {
-        if (!__any(active))
+    // the step loop is unrolled over SMAX so that every register index below
+    // is a compile-time constant (no select chains or copies)
+#pragma unroll
+    for (int k = 0; k < SMAX; ++k) {
+        if (k >= s || !__any(active))
             break;
         // 1. masked argmax over the group, lowest index on ties
         float best = -1.f;
@@ -224,7 +227,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         for (int t = 0; t < US; ++t) {
             w[t] = 0.f;
             if (t < k) {
-                float wt = acc / Lrow[t];     // meaningful in lane t
+                float wt = acc * rdg;         // meaningful in lane t
                 switch (t) {                  // broadcast lane t of the group
 #define DL_BCAST_CASE(T) \
     case T:              \
@@ -316,7 +319,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
             for (int t = 0; t < SMAX; ++t)
                 if (t == k) {
                     cv[t] = ck;
-                    dg[t] = delta;
+                    dgi[t] = inv;
                     js[t] = j;
                 }
             if (l == k) {
@@ -328,6 +331,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
                 for (int t = 0; t < SMAX; ++t)
                     if (t == k)
                         Lrow[t] = delta;
+                rdg = inv;
                 selj = j;
             }
             kg = k + 1;
@@ -343,7 +347,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
     for (int r = SMAX - 1; r >= 0; --r) {
         const float part = (l > r && l < kg) ? Lrow[r] * xown : 0.f;
         const float ssum = group_sum<LPS>(part);
-        const float xr = (cv[r] - ssum) / dg[r];
+        const float xr = (cv[r] - ssum) * dgi[r];
         xs[r] = r < kg ? xr : 0.f;
         if (l == r)
             xown = xs[r];
@@ -355,19 +359,23 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         a.idx[(size_t)io * s + l] = on ? selj : -1;
         a.val[(size_t)io * s + l] = on ? xown : 0.f;
     }
-    // residual e = y - D_I x with the dictionary used for coding
+    // residual e = y - D_I x with the dictionary used for coding; slots past
+    // kg hold atom 0 with a zero coefficient, so the row loads need no
+    // per-lane branch and are in flight together
     if (a.E || a.rnorm) {
         float esq = 0.f;
         if (valid)
             for (int q = 4 * l; q < p; q += 4 * LPS) {
                 f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
+                f32x4 d[SMAX];
 #pragma unroll
                 for (int t = 0; t < SMAX; ++t)
-                    if (t < kg) {
-                        const f32x4 d =
-                            *reinterpret_cast<const f32x4 *>(a.D + (size_t)js[t] * p + q);
-                        e -= d * xs[t];
-                    }
+                    if (t < s)
+                        d[t] = *reinterpret_cast<const f32x4 *>(a.D + (size_t)js[t] * p + q);
+#pragma unroll
+                for (int t = 0; t < SMAX; ++t)
+                    if (t < s)
+                        e -= d[t] * xs[t];
                 if (a.E)
                     *reinterpret_cast<f32x4 *>(a.E + (size_t)io * p + q) = e;
                 esq += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + e[3] * e[3];

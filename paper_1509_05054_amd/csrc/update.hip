@@ -276,13 +276,36 @@ __global__ __launch_bounds__(256) void eupdate_kernel(UpdateArgs a, int a0, int 
 }
 
 // ---- error ||Y - D X||_F^2 with an FP64 reduction ------------------------
-// One workgroup per block of kRmseSignals signals: the block's X rows are
-// staged in LDS, each lane group forms one residual row at a time, squares
-// are accumulated in FP64; the last workgroup to finish sums the per-block
-// partials in block order.
+// One workgroup per block of kRmseSignals signals (few workgroups, so few
+// arrivals at the shared counter): the block's X rows are staged in LDS, each
+// lane group forms residual rows 4 coordinates per lane with its atom rows
+// loaded four at a time (branch-free, so the loads are in flight together),
+// squares are summed in FP64; the last workgroup to finish sums the
+// per-block partials in block order.
+__device__ inline double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum of v over the workgroup (256 threads), in a fixed order; every thread
+// gets the result.
+__device__ inline double block_sum_f64(double v, double *red4)
+{
+    v = wave_sum_f64(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        red4[wave] = v;
+    __syncthreads();
+    return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
 __device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
 {
-    __shared__ double red[256];
+    __shared__ double red4[4];
     __shared__ int sIdx[kRmseSignals * 16];
     __shared__ float sVal[kRmseSignals * 16];
     __shared__ bool am_last;
@@ -295,8 +318,14 @@ __device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
     const int i0 = blk * kRmseSignals;
     const int nsig = min(kRmseSignals, a.m - i0);
     for (int r = threadIdx.x; r < nsig * s; r += blockDim.x) {
-        sIdx[r] = a.idx[(size_t)i0 * s + r];
-        sVal[r] = a.val[(size_t)i0 * s + r];
+        int j = a.idx[(size_t)i0 * s + r];
+        float x = a.val[(size_t)i0 * s + r];
+        if (j < 0 || j >= n) {
+            j = 0;  // unused slot: row 0 with a zero coefficient
+            x = 0.f;
+        }
+        sIdx[r] = j;
+        sVal[r] = x;
     }
     __syncthreads();
     double acc = 0.0;
@@ -304,26 +333,27 @@ __device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
         for (int il = wave * upw + sub; il < nsig; il += 4 * upw) {
             const int i = i0 + il;
             f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
-            for (int t = 0; t < s; ++t) {
-                const int j = sIdx[il * s + t];
-                if (j < 0 || j >= n)
-                    continue;
-                e -= *reinterpret_cast<const f32x4 *>(a.D + (size_t)j * p + q) * sVal[il * s + t];
+            for (int t0 = 0; t0 < s; t0 += 4) {
+                f32x4 d[4];
+                float x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int t = t0 + u < s ? t0 + u : t0;
+                    x[u] = t0 + u < s ? sVal[il * s + t] : 0.f;
+                    d[u] = *reinterpret_cast<const f32x4 *>(a.D + (size_t)sIdx[il * s + t] * p + q);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    e -= d[u] * x[u];
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 acc += (double)e[r] * (double)e[r];
         }
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
+    const double tot_blk = block_sum_f64(acc, red4);
     if (threadIdx.x == 0) {
-        a.partial[blk] = red[0];
+        a.partial[blk] = tot_blk;
         __threadfence();
         const unsigned prev = atomicAdd(&a.ctl->rmse_done, 1u);
         am_last = prev == (unsigned)nblk - 1;
@@ -335,15 +365,8 @@ __device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
         double v = 0.0;
         for (int b = threadIdx.x; b < nblk; b += blockDim.x)
             v += __hip_atomic_load(&a.partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w)
-                red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
+        const double tot = block_sum_f64(v, red4);
         if (threadIdx.x == 0) {
-            const double tot = red[0];
             a.out[0] = sqrt(tot / ((double)a.p * (double)a.m));
             if (!isfinite(tot))
                 atomicAdd(&a.ctl->nonfinite, 1ull);
