@@ -119,7 +119,7 @@ BatchLayout batch_layout(const dl_problem *probs, int count)
     L.norm = take(sizeof(NormArgs) * c);
     // 7 stage lists of count + 1 entries, and at most count shape lists of
     // (problems in the shape + 1) entries
-    L.lists_len = (int)(7 * (c + 1) + 2 * c);
+    L.lists_len = (int)(8 * (c + 1) + 2 * c);
     L.lists = take(sizeof(int32_t) * (size_t)L.lists_len);
     L.probs_begin = off;
     L.prob.resize(c);
@@ -139,8 +139,8 @@ struct Plan {
     std::vector<NormArgs> norm;   // [count]
     std::vector<int32_t> lists;
     // per stage: offset of its list in `lists` and its item total
-    int l_gemm, l_count, l_quad, l_scatter, l_chunk, l_rmse;
-    int n_gemm, n_count, n_quad, n_scatter, n_chunk, n_rmse;
+    int l_gemm, l_count, l_quad, l_scatter, l_chunk, l_rmse, l_one;
+    int n_gemm, n_count, n_quad, n_scatter, n_chunk, n_rmse, n_one;
     struct Shape {
         OmpShape sh;
         int first, num;  // problems [first, first + num) of the OMP table
@@ -268,6 +268,7 @@ void build_plan(const dl_problem *probs, int count, char *base, const BatchLayou
     add_list(it_scatter, P.l_scatter, P.n_scatter);
     add_list(it_chunk, P.l_chunk, P.n_chunk);
     add_list(it_rmse, P.l_rmse, P.n_rmse);
+    add_list(std::vector<int>(count, 1), P.l_one, P.n_one);
 
     // OMP: problems grouped by launch shape (shapes of larger groups first)
     P.shapes.clear();
@@ -403,7 +404,8 @@ dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void
                                   P.n_quad, list(P.l_scatter, count), P.n_scatter, P.max_n, st));
         DL_TRY(launch_batched_update(upd + par, list(P.l_chunk, count), P.n_chunk,
                                      list(P.l_quad, count), P.n_quad, st));
-        DL_TRY(launch_batched_rmse(rmse + par, list(P.l_rmse, count), P.n_rmse, k, st));
+        DL_TRY(launch_batched_rmse(rmse + par, list(P.l_rmse, count), P.n_rmse,
+                                   list(P.l_one, count), k, st));
     }
     if (iters % 2 == 1)
         for (int b = 0; b < count; ++b) {

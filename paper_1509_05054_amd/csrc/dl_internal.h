@@ -15,7 +15,7 @@ constexpr int kChunk = 256;
 // Signals per block of the CSR transpose (one workgroup each).
 constexpr int kCsrBlock = 256;
 // Signals per workgroup of the FP64 error reduction.
-constexpr int kRmseSignals = 64;
+constexpr int kRmseSignals = 16;
 
 // Device-side counters and control words at the start of the workspace.
 struct Control {
@@ -25,7 +25,7 @@ struct Control {
     unsigned long long zero_updates;
     unsigned long long nonfinite;
     unsigned long long fallbacks;
-    unsigned int rmse_done;  // arrival counter of the error reduction (self-resetting)
+    unsigned int rmse_done;  // (unused)
     unsigned int csr_done;   // arrival counter of the CSR offset scan (self-resetting)
     unsigned int pad[14];
 };
@@ -141,7 +141,7 @@ struct RmseArgs {
     const float *Y, *D;
     const int32_t *idx;
     const float *val;
-    double *partial;  // [rmse_blocks(m)]
+    double *partial;  // [rmse_blocks(m)] block partials
     double *out;      // one double
     Control *ctl;
     int p, n, m, s;
@@ -254,10 +254,10 @@ __device__ inline int batch_next_item(BatchQueue *q, int *slot)
 }
 
 // Called once by every worker after its last item; `workers` is the number
-// of workers in the launch.
+// of workers in the launch.  Only the counters are shared (results reach the
+// next launch through the launch boundary), so no fence is needed.
 __device__ inline void batch_leave(BatchQueue *q, unsigned workers)
 {
-    __threadfence();
     const unsigned prev = atomicAdd(&q->exited, 1u);
     if (prev == workers - 1) {
         atomicExch(&q->ticket, 0u);
@@ -287,8 +287,8 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
 hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
                                  int chunk_items, const BatchList &atom_list, int atom_items,
                                  hipStream_t st);
-hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items, int k,
-                               hipStream_t st);
+hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items,
+                               const BatchList &final_list, int k, hipStream_t st);
 hipError_t launch_batched_normalize(const NormArgs *tab, const BatchList &bl, int items,
                                     hipStream_t st);
 int omp_smax(int s);

@@ -85,7 +85,7 @@ __device__ inline void pass1_body(const UpdateArgs &a, int a0, int a1, int blk, 
         const f32x4 d = load4(a.D + (size_t)j * p, q, p);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         const int stride = 4 * upw;
-#pragma unroll 4
+#pragma unroll 8
         for (int r = wave * upw + sub; r < cnt; r += stride) {
             const int pos = sPos[r];
             const float x = sX[r];
@@ -200,24 +200,32 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
             const f32x4 d = load4(a.D + (size_t)j * p, q, p);
             const f32x4 dn = load4(a.Dn + (size_t)j * p, q, p);
             const int stride = 4 * upw;
-            // every lane of the wave runs the same trip count (shuffles below)
-#pragma unroll 2
-            for (int rb = wave * upw; rb < cnt; rb += stride) {
-                const int r = rb + sub;
-                const bool on = r < cnt;
-                float part = 0.f;
-                int pos = 0;
-                if (on) {
-                    pos = sPos[r];
-                    const float x = sX[r];
-                    const f32x4 e = load4(a.E + (size_t)(pos / s) * p, q, p);
-                    const f32x4 f = e + d * x;
-                    part = f[0] * dn[0] + f[1] * dn[1] + f[2] * dn[2] + f[3] * dn[3];
+            // every lane of the wave runs the same trip count (shuffles below);
+            // the residual rows of U users per lane are loaded before any of
+            // them is used, so their loads are in flight together
+            constexpr int U = 4;
+            for (int rb = wave * upw; rb < cnt; rb += stride * U) {
+                f32x4 e[U];
+                float x[U];
+                int pos[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int r = rb + u * stride + sub;
+                    const bool on = r < cnt;
+                    pos[u] = on ? sPos[r] : -1;
+                    x[u] = on ? sX[r] : 0.f;
+                    e[u] = on ? load4(a.E + (size_t)(pos[u] / s) * p, q, p)
+                              : f32x4{0.f, 0.f, 0.f, 0.f};
                 }
-                for (int off = 1; off < lpu; off <<= 1)
-                    part += __shfl_xor(part, off);
-                if (on && (lane % lpu) == 0)
-                    a.valn[pos] = part;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const f32x4 f = e[u] + d * x[u];
+                    float part = f[0] * dn[0] + f[1] * dn[1] + f[2] * dn[2] + f[3] * dn[3];
+                    for (int off = 1; off < lpu; off <<= 1)
+                        part += __shfl_xor(part, off);
+                    if (pos[u] >= 0 && (lane % lpu) == 0)
+                        a.valn[pos[u]] = part;
+                }
             }
         }
         __syncthreads();
@@ -276,12 +284,15 @@ __global__ __launch_bounds__(256) void eupdate_kernel(UpdateArgs a, int a0, int 
 }
 
 // ---- error ||Y - D X||_F^2 with an FP64 reduction ------------------------
-// One workgroup per block of kRmseSignals signals (few workgroups, so few
-// arrivals at the shared counter): the block's X rows are staged in LDS, each
-// lane group forms residual rows 4 coordinates per lane with its atom rows
-// loaded four at a time (branch-free, so the loads are in flight together),
-// squares are summed in FP64; the last workgroup to finish sums the
-// per-block partials in block order.
+// Two launches.  Partials: one workgroup per block of kRmseSignals signals;
+// the block's X rows are staged in LDS, each lane group forms residual rows 4
+// coordinates per lane with its atom rows loaded four at a time (branch-free,
+// so the loads are in flight together), squares are summed in FP64 and the
+// block's sum is stored.  Final: one workgroup sums the block partials in
+// block order.  The launch boundary orders the two, so no workgroup needs a
+// device-scope fence (which writes the L2 back on a multi-XCD GPU).
+__host__ __device__ inline int rmse_blocks_dev(int m) { return (m + kRmseSignals - 1) / kRmseSignals; }
+
 __device__ inline double wave_sum_f64(double v)
 {
 #pragma unroll
@@ -303,12 +314,11 @@ __device__ inline double block_sum_f64(double v, double *red4)
     return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
-__device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
+__device__ inline void rmse_body(const RmseArgs &a, int blk)
 {
     __shared__ double red4[4];
     __shared__ int sIdx[kRmseSignals * 16];
     __shared__ float sVal[kRmseSignals * 16];
-    __shared__ bool am_last;
     const int p = a.p, s = a.s, n = a.n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpu = lanes_per_user(p);
@@ -328,56 +338,74 @@ __device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
         sVal[r] = x;
     }
     __syncthreads();
+    // a lane group's signals il0, il0 + G, il0 + 2G, ... (G groups in the
+    // block) are formed together, so all their loads are in flight at once
+    constexpr int RU = 4;
+    const int G = 4 * upw;
     double acc = 0.0;
     if (q < p) {
-        for (int il = wave * upw + sub; il < nsig; il += 4 * upw) {
-            const int i = i0 + il;
-            f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
-            for (int t0 = 0; t0 < s; t0 += 4) {
-                f32x4 d[4];
-                float x[4];
+        for (int il0 = wave * upw + sub; il0 < nsig; il0 += G * RU) {
+            f32x4 e[RU];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int t = t0 + u < s ? t0 + u : t0;
-                    x[u] = t0 + u < s ? sVal[il * s + t] : 0.f;
-                    d[u] = *reinterpret_cast<const f32x4 *>(a.D + (size_t)sIdx[il * s + t] * p + q);
+            for (int u = 0; u < RU; ++u) {
+                const int il = il0 + u * G;
+                e[u] = il < nsig ? *reinterpret_cast<const f32x4 *>(a.Y + (size_t)(i0 + il) * p + q)
+                                 : f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+            for (int t0 = 0; t0 < s; t0 += 4) {
+                f32x4 d[RU][4];
+                float x[RU][4];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const int il = il0 + u * G < nsig ? il0 + u * G : il0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int t = t0 + v < s ? t0 + v : t0;
+                        x[u][v] = (t0 + v < s && il0 + u * G < nsig) ? sVal[il * s + t] : 0.f;
+                        d[u][v] = *reinterpret_cast<const f32x4 *>(a.D + (size_t)sIdx[il * s + t] * p + q);
+                    }
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    e -= d[u] * x[u];
+                for (int u = 0; u < RU; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        e[u] -= d[u][v] * x[u][v];
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc += (double)e[r] * (double)e[r];
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc += (double)e[u][r] * (double)e[u][r];
         }
     }
     const double tot_blk = block_sum_f64(acc, red4);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
         a.partial[blk] = tot_blk;
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.ctl->rmse_done, 1u);
-        am_last = prev == (unsigned)nblk - 1;
-    }
-    __syncthreads();
-    if (am_last) {
-        __threadfence();
-        // fixed-order final sum over the blocks' partials
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-            v += __hip_atomic_load(&a.partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double tot = block_sum_f64(v, red4);
-        if (threadIdx.x == 0) {
-            a.out[0] = sqrt(tot / ((double)a.p * (double)a.m));
-            if (!isfinite(tot))
-                atomicAdd(&a.ctl->nonfinite, 1ull);
-            a.ctl->rmse_done = 0;  // ready for the next call
-        }
+}
+
+// Sum of the nblk block partials in block order, and the error.
+__device__ inline void rmse_final_body(const RmseArgs &a, int nblk)
+{
+    __shared__ double red4[4];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        v += a.partial[b];
+    const double tot = block_sum_f64(v, red4);
+    if (threadIdx.x == 0) {
+        a.out[0] = sqrt(tot / ((double)a.p * (double)a.m));
+        if (!isfinite(tot))
+            atomicAdd(&a.ctl->nonfinite, 1ull);
     }
 }
 
 __global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
 {
-    rmse_body(a, blockIdx.x, gridDim.x);
+    rmse_body(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void rmse_final_kernel(RmseArgs a, int nblk)
+{
+    rmse_final_body(a, nblk);
 }
 
 __global__ __launch_bounds__(256) void residual_kernel(const float *__restrict__ Y,
@@ -474,9 +502,26 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restri
         batch_leave(bl.q, gridDim.x);
 }
 
-// The error of iteration k goes to out[k] of every problem.
-__global__ __launch_bounds__(256) void rmse_batched(const RmseArgs *__restrict__ tab, BatchList bl,
-                                                    int k)
+// Block partials of every problem; the error of iteration k then goes to
+// out[k] of every problem (rmse_final_batched).
+__global__ __launch_bounds__(256) void rmse_batched(const RmseArgs *__restrict__ tab, BatchList bl)
+{
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        rmse_body(tab[b], it - bl.start[b]);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
+}
+
+// One item per problem: its block partials in block order.
+__global__ __launch_bounds__(256) void rmse_final_batched(const RmseArgs *__restrict__ tab,
+                                                          BatchList bl, int k)
 {
     __shared__ int slot;
     const int total = bl.start[bl.count];
@@ -487,7 +532,7 @@ __global__ __launch_bounds__(256) void rmse_batched(const RmseArgs *__restrict__
         const int b = batch_find(bl.start, bl.count, it);
         RmseArgs a = tab[b];
         a.out += k;
-        rmse_body(a, it - bl.start[b], bl.start[b + 1] - bl.start[b]);
+        rmse_final_body(a, rmse_blocks_dev(a.m));
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -608,12 +653,19 @@ hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_l
     return hipGetLastError();
 }
 
-hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items, int k,
-                               hipStream_t st)
+hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items,
+                               const BatchList &final_list, int k, hipStream_t st)
 {
-    const int wg = batch_workers((const void *)rmse_batched, 256, 0, items);
+    int wg = batch_workers((const void *)rmse_batched, 256, 0, items);
     prof_begin(DL_K_RMSE, st);
-    hipLaunchKernelGGL(rmse_batched, dim3(wg), dim3(256), 0, st, tab, bl, k);
+    hipLaunchKernelGGL(rmse_batched, dim3(wg), dim3(256), 0, st, tab, bl);
+    prof_end(DL_K_RMSE, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    wg = batch_workers((const void *)rmse_final_batched, 256, 0, final_list.count);
+    prof_begin(DL_K_RMSE, st);
+    hipLaunchKernelGGL(rmse_final_batched, dim3(wg), dim3(256), 0, st, tab, final_list, k);
     prof_end(DL_K_RMSE, st);
     return hipGetLastError();
 }
@@ -630,8 +682,15 @@ hipError_t launch_batched_normalize(const NormArgs *tab, const BatchList &bl, in
 
 hipError_t launch_rmse(const RmseArgs &a, hipStream_t st)
 {
+    const int nb = rmse_blocks(a.m);
     prof_begin(DL_K_RMSE, st);
-    hipLaunchKernelGGL(rmse_kernel, dim3(rmse_blocks(a.m)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(rmse_kernel, dim3(nb), dim3(256), 0, st, a);
+    prof_end(DL_K_RMSE, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    prof_begin(DL_K_RMSE, st);
+    hipLaunchKernelGGL(rmse_final_kernel, dim3(1), dim3(256), 0, st, a, nb);
     prof_end(DL_K_RMSE, st);
     return hipGetLastError();
 }
