@@ -114,6 +114,22 @@ __device__ inline float group_bcast(float v)
 template <int NPL>
 using vec_t = float __attribute__((ext_vector_type(NPL)));
 
+template <int K>
+struct IntC {
+    static constexpr int value = K;
+};
+
+// f(IntC<K>) for K = B, B+1, ... < E while f returns true: the body is
+// instantiated once per K, so K is a compile-time constant inside it.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        if (f(IntC<B>{}))
+            static_for<B + 1, E>(f);
+    }
+}
+
 template <int NPL>
 __device__ inline void load_row(vec_t<NPL> &v, const float *row, int first, int ldn, bool on)
 {
@@ -191,12 +207,12 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         atomicAdd(&a.ctl->nonfinite, 1ull);
     int kg = 0;  // atoms selected for this lane's signal
 
-    // the step loop is unrolled over SMAX so that every register index below
-    // is a compile-time constant (no select chains or copies)
-#pragma unroll
-    for (int k = 0; k < SMAX; ++k) {
+    // the steps are expanded at compile time (static_for), so that every
+    // register index below is a constant: no select chains or copies
+    static_for<0, SMAX>([&](auto kc) -> bool {
+        constexpr int k = decltype(kc)::value;
         if (k >= s || !__any(active))
-            break;
+            return false;
         // 1. masked argmax over the group, lowest index on ties
         float best = -1.f;
         int bidx = 0x7fffffff;
@@ -336,7 +352,8 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
             }
             kg = k + 1;
         }
-    }
+        return true;
+    });
     if (valid && l == 0 && kg < s)
         atomicAdd(&a.ctl->early_stops, 1ull);
 
