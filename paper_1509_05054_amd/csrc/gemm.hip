@@ -25,19 +25,50 @@ constexpr int kTN = 4;                // 16x16 MFMA tiles per wave along N
 constexpr int kBlockM = 2 * 16 * kTM; // 2 x 2 waves per workgroup
 constexpr int kBlockN = 2 * 16 * kTN;
 
-__device__ inline void store_tile(float *C, int M, int N, int ldc, int row0, int col0,
-                                  const f32x4 &acc, int lane)
+// The workgroup's tile is written through LDS so that global stores cover
+// whole contiguous row segments (the MFMA output layout gives each store
+// instruction four 64-byte pieces of different rows).  acc[a][b] holds the
+// 16x16 tile (a, b) of the calling wave; rows/cols are relative to the
+// workgroup tile at (brow0, bcol0) of height BM.
+constexpr int kStageLd = kBlockN + 4;
+
+template <int TM, int BM>
+__device__ inline void store_block(float *C, int M, int N, int ldc, int brow0, int bcol0,
+                                   const f32x4 (&acc)[TM][kTN], float *sC)
 {
-    const int col = col0 + (lane & 15);
-    const int rbase = row0 + 4 * (lane >> 4);
-    if (col >= N)
-        return;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 16 * TM, wc = (wave & 1) * 16 * kTN;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = rbase + r;
-        if (row < M)
-            C[(size_t)row * ldc + col] = acc[r];
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < kTN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sC[(wr + 16 * a + 4 * (lane >> 4) + r) * kStageLd + wc + 16 * b + (lane & 15)] =
+                    acc[a][b][r];
+    __syncthreads();
+    // 32 lanes per row, 4 columns each: 8 rows per pass of the workgroup;
+    // 16-byte stores when C and its row stride allow them
+    const bool vec_ok = (ldc % 4) == 0 && ((uintptr_t)C % 16) == 0;
+    const int cc = 4 * (threadIdx.x & 31);
+    const int col = bcol0 + cc;
+#pragma unroll
+    for (int r0 = 0; r0 < BM; r0 += 8) {
+        const int rr = r0 + (int)(threadIdx.x >> 5);
+        const int row = brow0 + rr;
+        if (row >= M || col >= N)
+            continue;
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(sC + rr * kStageLd + cc);
+        float *dst = C + (size_t)row * ldc + col;
+        if (vec_ok && col + 3 < N) {
+            *reinterpret_cast<f32x4 *>(dst) = v;
+        } else {
+            for (int q = 0; q < 4 && col + q < N; ++q)
+                dst[q] = v[q];
+        }
     }
+    __syncthreads();  // sC is reused by the next tile of a persistent workgroup
 }
 
 // Which of the (up to two) problems of a grouped launch this workgroup
@@ -110,11 +141,8 @@ __device__ inline void gemm_f32_tile(const GemmF32 &P, int brow0, int bcol0)
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h][a][q], bv[h][b][q],
                                                                           acc[a][b], 0, 0, 0);
     }
-#pragma unroll
-    for (int a = 0; a < kTM; ++a)
-#pragma unroll
-        for (int b = 0; b < kTN; ++b)
-            store_tile(P.C, M, N, P.ldc, row0 + 16 * a, col0 + 16 * b, acc[a][b], lane);
+    __shared__ float sC[32 * TM * kStageLd];
+    store_block<TM, 32 * TM>(P.C, M, N, P.ldc, brow0, bcol0, acc, sC);
 }
 
 // FP32 products use workgroup tiles of kF32M rows (64: measured faster than
@@ -219,11 +247,8 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmBF16 p0, GemmBF16
                     __builtin_bit_cast(bf16x8, av[a]), __builtin_bit_cast(bf16x8, bv[b]),
                     acc[a][b], 0, 0, 0);
     }
-#pragma unroll
-    for (int a = 0; a < kTM; ++a)
-#pragma unroll
-        for (int b = 0; b < kTN; ++b)
-            store_tile(P.C, M, N, P.ldc, row0 + 16 * a, col0 + 16 * b, acc[a][b], lane);
+    __shared__ float sC[kBlockM * kStageLd];
+    store_block<kTM, kBlockM>(P.C, M, N, P.ldc, brow0, bcol0, acc, sC);
 }
 
 // Round-to-nearest-even FP32 -> BF16 on the bit pattern (NaN kept quiet).
