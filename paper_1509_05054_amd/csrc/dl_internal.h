@@ -285,8 +285,7 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
                               const BatchList &scatter_list, int scatter_items, int max_n,
                               hipStream_t st);
 hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
-                                 int chunk_items, const BatchList &atom_list, int atom_items,
-                                 hipStream_t st);
+                                 int chunk_items, hipStream_t st);
 hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items,
                                const BatchList &final_list, int k, hipStream_t st);
 hipError_t launch_batched_normalize(const NormArgs *tab, const BatchList &bl, int items,

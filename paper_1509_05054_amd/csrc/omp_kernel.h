@@ -52,13 +52,20 @@ __device__ inline int dpp(int v)
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
-// Combine (value, index) pairs: larger value wins, lower index on ties.
+// A DPP lane permutation that every lane takes part in (no bound control).
+template <int CTRL>
+__device__ inline int dpp_all(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
+// Combine (value, index) pairs: larger value wins, lower index on ties
+// (selects, no branch).
 __device__ inline void take_better(float &v, int &ix, float ov, int oi)
 {
-    if (ov > v || (ov == v && oi < ix)) {
-        v = ov;
-        ix = oi;
-    }
+    const bool b = ov > v || (ov == v && oi < ix);
+    v = b ? ov : v;
+    ix = b ? oi : ix;
 }
 
 // All-reduce of (max value, lowest index) over groups of LPS lanes.
@@ -66,13 +73,13 @@ template <int LPS>
 __device__ inline void group_argmax(float &v, int &ix)
 {
     if constexpr (LPS >= 2)
-        take_better(v, ix, bits_f(dpp<0xB1>(f_bits(v))), dpp<0xB1>(ix));      // lane ^ 1
+        take_better(v, ix, bits_f(dpp_all<0xB1>(f_bits(v))), dpp_all<0xB1>(ix));    // lane ^ 1
     if constexpr (LPS >= 4)
-        take_better(v, ix, bits_f(dpp<0x4E>(f_bits(v))), dpp<0x4E>(ix));      // lane ^ 2
+        take_better(v, ix, bits_f(dpp_all<0x4E>(f_bits(v))), dpp_all<0x4E>(ix));    // lane ^ 2
     if constexpr (LPS >= 8)
-        take_better(v, ix, bits_f(dpp<0x141>(f_bits(v))), dpp<0x141>(ix));    // half-row mirror
+        take_better(v, ix, bits_f(dpp_all<0x141>(f_bits(v))), dpp_all<0x141>(ix));  // half-row mirror
     if constexpr (LPS >= 16)
-        take_better(v, ix, bits_f(dpp<0x140>(f_bits(v))), dpp<0x140>(ix));    // row mirror
+        take_better(v, ix, bits_f(dpp_all<0x140>(f_bits(v))), dpp_all<0x140>(ix));  // row mirror
     if constexpr (LPS >= 32)
         take_better(v, ix, __shfl_xor(v, 16), __shfl_xor(ix, 16));
     if constexpr (LPS >= 64)
@@ -219,10 +226,9 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
 #pragma unroll
         for (int c = 0; c < NPL; ++c) {
             const float v = fabsf(alpha[c]);
-            if (!((taken >> c) & 1u) && v > best) {
-                best = v;
-                bidx = a_first + c;
-            }
+            const bool b = !((taken >> c) & 1u) && v > best;
+            best = b ? v : best;
+            bidx = b ? a_first + c : bidx;
         }
         group_argmax<LPS>(best, bidx);
         bool ok = active && best > thr && bidx < n;

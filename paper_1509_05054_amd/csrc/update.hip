@@ -6,11 +6,11 @@
 //   pass 1 : g_j = F x_j^T = sum_{i in I_j} (e_i + d_j x_ji) x_ji   (eq. 3)
 //            over chunks of kChunk users, one workgroup per chunk, partial
 //            sums written per chunk (no float atomics);
-//   reduce : g_j summed over its chunks in chunk order, d_j' = g_j / ||g_j||
-//            (eq. 5, first line; SGK's least-squares atom has the same
-//            direction), written to the next dictionary Dn;
-//   pass 2 : AK-SVD refresh x_ji' = (e_i + d_j x_ji)^T d_j' (eq. 5, second
-//            line), written to valn;
+//   pass 2 : per chunk, g_j summed over the atom's chunks in chunk order and
+//            d_j' = g_j / ||g_j|| (eq. 5, first line; SGK's least-squares
+//            atom has the same direction), written to the next dictionary Dn
+//            by the atom's first chunk; then the AK-SVD refresh
+//            x_ji' = (e_i + d_j x_ji)^T d_j' (eq. 5, second line) to valn;
 //   E      : for group sizes below n, E is brought up to date for the next
 //            group: e_i += d_j x_ji - d_j' x_ji' over the group's atoms that
 //            signal i uses (the incremental error update the paper mentions
@@ -113,80 +113,69 @@ __global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1
     pass1_body(a, a0, a1, blockIdx.x, gridDim.x);
 }
 
-// ---- reduce over chunks + normalise (one wave per atom) -----------------
-__device__ inline void reduce_body(const UpdateArgs &a, int a0, int a1, int blk)
+// ---- pass 2: d_j' and the AK-SVD representation refresh ------------------
+// Every chunk of atom j sums the atom's chunk partials in chunk order (so
+// every chunk gets the same bits), normalises (d_j' = g_j / ||g_j||, eq. 5
+// first line; SGK's least-squares atom has the same direction) and refreshes
+// its users x_ji' = (e_i + d_j x_ji)^T d_j' (eq. 5, second line).  The first
+// chunk of the atom writes d_j' to Dn and the atom's state.  Atoms without
+// users keep d_j; the items after the chunks handle them.
+__device__ inline float block_sum_f32(float v, float *red4)
 {
-    const int p = a.p;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = a0 + blk * 4 + wave;
-    if (j >= a1)
-        return;
-    const int c0 = a.chunk_ptr[j], c1 = a.chunk_ptr[j + 1];
-    float g[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int c = c0; c < c1; ++c)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int q = lane + 64 * r;
-            if (q < p)
-                g[r] += a.partial[(size_t)c * p + q];
-        }
-    float sq = 0.f;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        sq += g[r] * g[r];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
-        sq += __shfl_xor(sq, off);
-    int state;
-    if (c1 == c0)
-        state = 1;  // no users: d_j unchanged
-    else if (!(sq > 0.f))
-        state = 2;  // F x^T = 0 (or not finite): unchanged
-    else
-        state = 0;
-    const float inv = state == 0 ? 1.0f / sqrtf(sq) : 0.f;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int q = lane + 64 * r;
-        if (q < p)
-            a.Dn[(size_t)j * p + q] = state == 0 ? g[r] * inv : a.D[(size_t)j * p + q];
-    }
-    if (lane == 0) {
-        a.atom_state[j] = state;
-        if (state == 1)
-            atomicAdd(&a.ctl->unused_atoms, 1ull);
-        else if (state == 2) {
-            atomicAdd(&a.ctl->zero_updates, 1ull);
-            if (!(sq == 0.f))
-                atomicAdd(&a.ctl->nonfinite, 1ull);
-        }
-    }
+        v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
-__global__ __launch_bounds__(256) void reduce_kernel(UpdateArgs a, int a0, int a1)
-{
-    reduce_body(a, a0, a1, blockIdx.x);
-}
-
-// ---- pass 2: AK-SVD representation refresh ------------------------------
 __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, int nblk)
 {
     __shared__ int sPos[kChunk];
     __shared__ float sX[kChunk];
+    __shared__ float sDn[256];
+    __shared__ float red4[4];
     const int p = a.p, s = a.s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpu = lanes_per_user(p);
     const int upw = 64 / lpu;
     const int sub = lane / lpu;
     const int q = 4 * (lane % lpu);
+    const int t = threadIdx.x;  // coordinate of d_j' owned by this thread
     const int cbase = a.chunk_ptr[a0];
     const int nch = a.chunk_ptr[a1] - cbase;
     for (int c = blk; c < nch; c += nblk) {
         const int gc = cbase + c;
         const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
-        const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
+        const int c0 = a.chunk_ptr[j], c1 = a.chunk_ptr[j + 1];
+        const int u0 = a.row_ptr[j] + (gc - c0) * kChunk;
         const int cnt = min(kChunk, a.row_ptr[j + 1] - u0);
-        const bool keep = a.rule != DL_RULE_AKSVD || a.atom_state[j] != 0;
+        // g_j = sum of the atom's chunk partials, in chunk order
+        float g = 0.f;
+        if (t < p)
+            for (int cc = c0; cc < c1; ++cc)
+                g += a.partial[(size_t)cc * p + t];
+        const float sq = block_sum_f32(g * g, red4);
+        const int state = sq > 0.f ? 0 : 2;  // 2: F x^T = 0 (or not finite): unchanged
+        const float inv = state == 0 ? 1.0f / sqrtf(sq) : 0.f;
+        if (t < p) {
+            const float dn = state == 0 ? g * inv : a.D[(size_t)j * p + t];
+            sDn[t] = dn;
+            if (gc == c0)
+                a.Dn[(size_t)j * p + t] = dn;
+        }
+        if (gc == c0 && t == 0) {
+            a.atom_state[j] = state;
+            if (state == 2) {
+                atomicAdd(&a.ctl->zero_updates, 1ull);
+                if (!(sq == 0.f))
+                    atomicAdd(&a.ctl->nonfinite, 1ull);
+            }
+        }
+        const bool keep = a.rule != DL_RULE_AKSVD || state != 0;
         for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
             const int pos = a.users[u0 + r];
             sPos[r] = pos;
@@ -198,7 +187,8 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
                 a.valn[sPos[r]] = sX[r];
         } else {
             const f32x4 d = load4(a.D + (size_t)j * p, q, p);
-            const f32x4 dn = load4(a.Dn + (size_t)j * p, q, p);
+            const f32x4 dn = q < p ? *reinterpret_cast<const f32x4 *>(sDn + q)
+                                   : f32x4{0.f, 0.f, 0.f, 0.f};
             const int stride = 4 * upw;
             // every lane of the wave runs the same trip count (shuffles below);
             // the residual rows of U users per lane are loaded before any of
@@ -229,6 +219,18 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
             }
         }
         __syncthreads();
+    }
+    // atoms without users: d_j unchanged (one wave per atom)
+    for (int qd = blk; qd < (a1 - a0 + 3) / 4; qd += nblk) {
+        const int j = a0 + 4 * qd + wave;
+        if (j >= a1 || a.chunk_ptr[j + 1] != a.chunk_ptr[j])
+            continue;
+        for (int k = lane; k < p; k += 64)
+            a.Dn[(size_t)j * p + k] = a.D[(size_t)j * p + k];
+        if (lane == 0) {
+            a.atom_state[j] = 1;
+            atomicAdd(&a.ctl->unused_atoms, 1ull);
+        }
     }
 }
 
@@ -476,7 +478,8 @@ __global__ __launch_bounds__(256) void normalize_kernel(float *D, int n, int p, 
 
 // ---- batched problems (one group per problem: atoms [0, n)) --------------
 // Items: pass 1 and pass 2 = chunk slots (an upper bound of the chunks; the
-// excess leaves at once), reduce = atom quads, error = signal blocks,
+// excess leaves at once, and pass 2's slots also cover the atom quads of its
+// unused-atom step), error = signal blocks,
 // normalisation = atom quads.
 template <int STAGE>
 __global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restrict__ tab,
@@ -493,8 +496,6 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restri
         const int t = it - bl.start[b], nt = bl.start[b + 1] - bl.start[b];
         if (STAGE == 0)
             pass1_body(a, 0, a.n, t, nt);
-        else if (STAGE == 1)
-            reduce_body(a, 0, a.n, t);
         else
             pass2_body(a, 0, a.n, t, nt);
     }
@@ -607,11 +608,6 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
-        prof_begin(DL_K_UPD_REDUCE, st);
-        hipLaunchKernelGGL(reduce_kernel, dim3((a1 - a0 + 3) / 4), dim3(256), 0, st, a, a0, a1);
-        prof_end(DL_K_UPD_REDUCE, st);
-        if ((e = hipGetLastError()) != hipSuccess)
-            return e;
         prof_begin(DL_K_UPD_PASS2, st);
         hipLaunchKernelGGL(pass2_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
         prof_end(DL_K_UPD_PASS2, st);
@@ -630,8 +626,7 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
 }
 
 hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
-                                 int chunk_items, const BatchList &atom_list, int atom_items,
-                                 hipStream_t st)
+                                 int chunk_items, hipStream_t st)
 {
     int wg = batch_workers((const void *)update_batched<0>, 256, 0, chunk_items);
     prof_begin(DL_K_UPD_PASS1, st);
@@ -639,12 +634,6 @@ hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_l
     prof_end(DL_K_UPD_PASS1, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
-        return e;
-    wg = batch_workers((const void *)update_batched<1>, 256, 0, atom_items);
-    prof_begin(DL_K_UPD_REDUCE, st);
-    hipLaunchKernelGGL(update_batched<1>, dim3(wg), dim3(256), 0, st, tab, atom_list);
-    prof_end(DL_K_UPD_REDUCE, st);
-    if ((e = hipGetLastError()) != hipSuccess)
         return e;
     wg = batch_workers((const void *)update_batched<2>, 256, 0, chunk_items);
     prof_begin(DL_K_UPD_PASS2, st);
