@@ -8,9 +8,9 @@
 //             popcount of the lower bits, and per-wave running counts rank
 //             the chunks.  Result: per-(atom, block) counts and, per entry,
 //             its rank among the block's uses of the atom.
-//   scan    : one wave per atom scans its per-block counts into offsets; the
-//             last workgroup to finish scans the atom totals into row_ptr
-//             (and chunk_ptr, the update's chunks of kChunk users).
+//   scan    : one wave per atom scans its per-block counts into offsets and
+//             its total; a one-workgroup launch then scans the atom totals
+//             into row_ptr (and chunk_ptr, the update's chunks of kChunk users).
 //   scatter : one thread per entry: users[row_ptr + offset + rank] = entry.
 // Entries of an atom end up in increasing (signal, slot) order, so the
 // result is unique and the atom update's summation order is fixed.
@@ -118,50 +118,47 @@ __device__ inline int wave_inclusive_scan(int x)
     return x;
 }
 
-// Per atom: per-block counts -> offsets inside the atom's user list, and the
-// atom total.  The last workgroup scans the totals into row_ptr / chunk_ptr.
-// Item blk (atoms 4 blk .. 4 blk + 3) of nblk items of the scan.
+// Per atom (one wave each): per-block counts -> offsets inside the atom's
+// user list, and the atom total.  Item blk covers atoms 4 blk .. 4 blk + 3.
 __device__ inline void csr_scan_body(int32_t *__restrict__ blkcnt, int32_t *__restrict__ tot,
-                                     int32_t *__restrict__ row_ptr,
-                                     int32_t *__restrict__ chunk_ptr, Control *ctl, int n, int nb,
-                                     int blk, int nblk)
+                                     int n, int nb, int blk)
 {
-    __shared__ int sh[2][4];
-    __shared__ bool am_last;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int a = blk * 4 + wave;
-    if (a < n) {
-        int carry = 0;
-        for (int b0 = 0; b0 < nb; b0 += 64) {
-            const int b = b0 + lane;
-            const int v = b < nb ? blkcnt[(size_t)a * nb + b] : 0;
-            const int x = wave_inclusive_scan(v);
-            if (b < nb)
-                blkcnt[(size_t)a * nb + b] = carry + x - v;
-            carry += __shfl(x, 63);
-        }
-        if (lane == 0)
-            tot[a] = carry;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&ctl->csr_done, 1u);
-        am_last = prev == (unsigned)nblk - 1;
-    }
-    __syncthreads();
-    if (!am_last)
+    if (a >= n)
         return;
-    __threadfence();
-    // exclusive scan of the atom totals: thread t owns atoms [t*per, (t+1)*per)
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+        const int b = b0 + lane;
+        const int v = b < nb ? blkcnt[(size_t)a * nb + b] : 0;
+        const int x = wave_inclusive_scan(v);
+        if (b < nb)
+            blkcnt[(size_t)a * nb + b] = carry + x - v;
+        carry += __shfl(x, 63);
+    }
+    if (lane == 0)
+        tot[a] = carry;
+}
+
+// Exclusive scan of the atom totals into row_ptr, and of their chunk counts
+// (kChunk users per chunk) into chunk_ptr; one workgroup, thread t owning
+// atoms [t*per, (t+1)*per).  A launch of its own after the per-atom scan, so
+// the totals need no device-scope fence.
+__device__ inline void csr_total_body(const int32_t *__restrict__ tot,
+                                      int32_t *__restrict__ row_ptr,
+                                      int32_t *__restrict__ chunk_ptr, int n)
+{
+    __shared__ int sh[2][4];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const int per = (n + 255) / 256;
     const int a0 = threadIdx.x * per;
     int su = 0, sc = 0;
     for (int q = 0; q < per; ++q) {
         const int aa = a0 + q;
         if (aa < n) {
-            const int v = __hip_atomic_load(&tot[aa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int v = tot[aa];
             su += v;
             sc += (v + kChunk - 1) / kChunk;
         }
@@ -186,7 +183,7 @@ __device__ inline void csr_scan_body(int32_t *__restrict__ blkcnt, int32_t *__re
     for (int q = 0; q < per; ++q) {
         const int aa = a0 + q;
         if (aa < n) {
-            const int v = __hip_atomic_load(&tot[aa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int v = tot[aa];
             row_ptr[aa] = ru;
             chunk_ptr[aa] = rc;
             ru += v;
@@ -196,17 +193,21 @@ __device__ inline void csr_scan_body(int32_t *__restrict__ blkcnt, int32_t *__re
     if (threadIdx.x == 0) {
         row_ptr[n] = tu;
         chunk_ptr[n] = tc;
-        ctl->csr_done = 0;  // ready for the next call
     }
+    __syncthreads();  // sh is reused by the next item of a persistent workgroup
 }
 
 __global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blkcnt,
-                                                       int32_t *__restrict__ tot,
-                                                       int32_t *__restrict__ row_ptr,
-                                                       int32_t *__restrict__ chunk_ptr,
-                                                       Control *ctl, int n, int nb)
+                                                       int32_t *__restrict__ tot, int n, int nb)
 {
-    csr_scan_body(blkcnt, tot, row_ptr, chunk_ptr, ctl, n, nb, blockIdx.x, gridDim.x);
+    csr_scan_body(blkcnt, tot, n, nb, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void csr_total_kernel(const int32_t *__restrict__ tot,
+                                                        int32_t *__restrict__ row_ptr,
+                                                        int32_t *__restrict__ chunk_ptr, int n)
+{
+    csr_total_body(tot, row_ptr, chunk_ptr, n);
 }
 
 __device__ inline void csr_scatter_body(const int32_t *__restrict__ idx,
@@ -273,8 +274,25 @@ __global__ __launch_bounds__(256) void csr_scan_batched(const CsrArgs *__restric
             break;
         const int b = batch_find(bl.start, bl.count, it);
         const CsrArgs a = tab[b];
-        csr_scan_body(a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.ctl, a.n, csr_nb(a.m),
-                      it - bl.start[b], bl.start[b + 1] - bl.start[b]);
+        csr_scan_body(a.blkcnt, a.tot, a.n, csr_nb(a.m), it - bl.start[b]);
+    }
+    if (threadIdx.x == 0)
+        batch_leave(bl.q, gridDim.x);
+}
+
+// One item per problem.
+__global__ __launch_bounds__(256) void csr_total_batched(const CsrArgs *__restrict__ tab,
+                                                         BatchList bl)
+{
+    __shared__ int slot;
+    const int total = bl.start[bl.count];
+    for (;;) {
+        const int it = batch_next_item(bl.q, &slot);
+        if (it >= total)
+            break;
+        const int b = batch_find(bl.start, bl.count, it);
+        const CsrArgs a = tab[b];
+        csr_total_body(a.tot, a.row_ptr, a.chunk_ptr, a.n);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -305,8 +323,8 @@ int csr_blocks(int m) { return (m + kCsrBlock - 1) / kCsrBlock; }
 // Items: count = signal blocks, scan = atom quads, scatter = blocks of 256 entries.
 hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, int count_items,
                               const BatchList &scan_list, int scan_items,
-                              const BatchList &scatter_list, int scatter_items, int max_n,
-                              hipStream_t st)
+                              const BatchList &total_list, const BatchList &scatter_list,
+                              int scatter_items, int max_n, hipStream_t st)
 {
     const size_t shmem = (sizeof(unsigned long long) + sizeof(int32_t)) * kWavesPerBlock * max_n;
     int wg = batch_workers((const void *)csr_count_batched, kCsrBlock, shmem, count_items);
@@ -319,6 +337,10 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
     wg = batch_workers((const void *)csr_scan_batched, 256, 0, scan_items);
     prof_begin(DL_K_CSR_SCAN, st);
     hipLaunchKernelGGL(csr_scan_batched, dim3(wg), dim3(256), 0, st, tab, scan_list);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    wg = batch_workers((const void *)csr_total_batched, 256, 0, total_list.count);
+    hipLaunchKernelGGL(csr_total_batched, dim3(wg), dim3(256), 0, st, tab, total_list);
     prof_end(DL_K_CSR_SCAN, st);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
@@ -342,7 +364,9 @@ hipError_t launch_csr(const CsrArgs &a, hipStream_t st)
         return e;
     prof_begin(DL_K_CSR_SCAN, st);
     hipLaunchKernelGGL(csr_scan_kernel, dim3((a.n + 3) / 4), dim3(256), 0, st, a.blkcnt, a.tot,
-                       a.row_ptr, a.chunk_ptr, a.ctl, a.n, nb);
+                       a.n, nb);
+    hipLaunchKernelGGL(csr_total_kernel, dim3(1), dim3(256), 0, st, a.tot, a.row_ptr,
+                       a.chunk_ptr, a.n);
     prof_end(DL_K_CSR_SCAN, st);
     e = hipGetLastError();
     if (e != hipSuccess)
