@@ -409,8 +409,11 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
     }
 }
 
+// Small sparsity bounds ask for three waves per SIMD (a few dwords spill;
+// measured faster than two waves without spills).
 template <int LPS, int NPL, int SMAX>
-__global__ __launch_bounds__(64 * kWaves) void omp_kernel(OmpArgs a)
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(SMAX <= 6 ? 3 : 1)))
+void omp_kernel(OmpArgs a)
 {
     constexpr int GPW = 64 / LPS;
     const int m_eff = a.m_dev ? min(*a.m_dev, a.m) : a.m;

@@ -293,7 +293,15 @@ __global__ __launch_bounds__(256) void eupdate_kernel(UpdateArgs a, int a0, int 
 // block's sum is stored.  Final: one workgroup sums the block partials in
 // block order.  The launch boundary orders the two, so no workgroup needs a
 // device-scope fence (which writes the L2 back on a multi-XCD GPU).
-__host__ __device__ inline int rmse_blocks_dev(int m) { return (m + kRmseSignals - 1) / kRmseSignals; }
+// Workgroups of the partials launch: one per kRmseSignals signals, at most
+// kRmseMaxBlocks (each then strides over several signal blocks), so the final
+// one-workgroup sum stays short.
+constexpr int kRmseMaxBlocks = 1024;
+__host__ __device__ inline int rmse_blocks_dev(int m)
+{
+    const int b = (m + kRmseSignals - 1) / kRmseSignals;
+    return b < kRmseMaxBlocks ? b : kRmseMaxBlocks;
+}
 
 __device__ inline double wave_sum_f64(double v)
 {
@@ -316,7 +324,7 @@ __device__ inline double block_sum_f64(double v, double *red4)
     return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
-__device__ inline void rmse_body(const RmseArgs &a, int blk)
+__device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
 {
     __shared__ double red4[4];
     __shared__ int sIdx[kRmseSignals * 16];
@@ -327,57 +335,61 @@ __device__ inline void rmse_body(const RmseArgs &a, int blk)
     const int upw = 64 / lpu;
     const int sub = lane / lpu;
     const int q = 4 * (lane % lpu);
-    const int i0 = blk * kRmseSignals;
-    const int nsig = min(kRmseSignals, a.m - i0);
-    for (int r = threadIdx.x; r < nsig * s; r += blockDim.x) {
-        int j = a.idx[(size_t)i0 * s + r];
-        float x = a.val[(size_t)i0 * s + r];
-        if (j < 0 || j >= n) {
-            j = 0;  // unused slot: row 0 with a zero coefficient
-            x = 0.f;
-        }
-        sIdx[r] = j;
-        sVal[r] = x;
-    }
-    __syncthreads();
-    // a lane group's signals il0, il0 + G, il0 + 2G, ... (G groups in the
-    // block) are formed together, so all their loads are in flight at once
-    constexpr int RU = 4;
-    const int G = 4 * upw;
     double acc = 0.0;
-    if (q < p) {
-        for (int il0 = wave * upw + sub; il0 < nsig; il0 += G * RU) {
-            f32x4 e[RU];
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                const int il = il0 + u * G;
-                e[u] = il < nsig ? *reinterpret_cast<const f32x4 *>(a.Y + (size_t)(i0 + il) * p + q)
-                                 : f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nsb = (a.m + kRmseSignals - 1) / kRmseSignals;
+    for (int sb = blk; sb < nsb; sb += nblk) {
+        const int i0 = sb * kRmseSignals;
+        const int nsig = min(kRmseSignals, a.m - i0);
+        __syncthreads();  // the previous signal block's rows are no longer read
+        for (int r = threadIdx.x; r < nsig * s; r += blockDim.x) {
+            int j = a.idx[(size_t)i0 * s + r];
+            float x = a.val[(size_t)i0 * s + r];
+            if (j < 0 || j >= n) {
+                j = 0;  // unused slot: row 0 with a zero coefficient
+                x = 0.f;
             }
-            for (int t0 = 0; t0 < s; t0 += 4) {
-                f32x4 d[RU][4];
-                float x[RU][4];
-#pragma unroll
+            sIdx[r] = j;
+            sVal[r] = x;
+        }
+        __syncthreads();
+        // a lane group's signals il0, il0 + G, il0 + 2G, ... (G groups in the
+        // block) are formed together, so all their loads are in flight at once
+        constexpr int RU = 4;
+        const int G = 4 * upw;
+        if (q < p) {
+            for (int il0 = wave * upw + sub; il0 < nsig; il0 += G * RU) {
+                f32x4 e[RU];
+    #pragma unroll
                 for (int u = 0; u < RU; ++u) {
-                    const int il = il0 + u * G < nsig ? il0 + u * G : il0;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int t = t0 + v < s ? t0 + v : t0;
-                        x[u][v] = (t0 + v < s && il0 + u * G < nsig) ? sVal[il * s + t] : 0.f;
-                        d[u][v] = *reinterpret_cast<const f32x4 *>(a.D + (size_t)sIdx[il * s + t] * p + q);
-                    }
+                    const int il = il0 + u * G;
+                    e[u] = il < nsig ? *reinterpret_cast<const f32x4 *>(a.Y + (size_t)(i0 + il) * p + q)
+                                     : f32x4{0.f, 0.f, 0.f, 0.f};
                 }
-#pragma unroll
+                for (int t0 = 0; t0 < s; t0 += 4) {
+                    f32x4 d[RU][4];
+                    float x[RU][4];
+    #pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        const int il = il0 + u * G < nsig ? il0 + u * G : il0;
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int t = t0 + v < s ? t0 + v : t0;
+                            x[u][v] = (t0 + v < s && il0 + u * G < nsig) ? sVal[il * s + t] : 0.f;
+                            d[u][v] = *reinterpret_cast<const f32x4 *>(a.D + (size_t)sIdx[il * s + t] * p + q);
+                        }
+                    }
+    #pragma unroll
+                    for (int u = 0; u < RU; ++u)
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            e[u] -= d[u][v] * x[u][v];
+                }
+    #pragma unroll
                 for (int u = 0; u < RU; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        e[u] -= d[u][v] * x[u][v];
+    #pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc += (double)e[u][r] * (double)e[u][r];
             }
-#pragma unroll
-            for (int u = 0; u < RU; ++u)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    acc += (double)e[u][r] * (double)e[u][r];
         }
     }
     const double tot_blk = block_sum_f64(acc, red4);
@@ -402,7 +414,7 @@ __device__ inline void rmse_final_body(const RmseArgs &a, int nblk)
 
 __global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
 {
-    rmse_body(a, blockIdx.x);
+    rmse_body(a, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void rmse_final_kernel(RmseArgs a, int nblk)
@@ -514,7 +526,7 @@ __global__ __launch_bounds__(256) void rmse_batched(const RmseArgs *__restrict__
         if (it >= total)
             break;
         const int b = batch_find(bl.start, bl.count, it);
-        rmse_body(tab[b], it - bl.start[b]);
+        rmse_body(tab[b], it - bl.start[b], bl.start[b + 1] - bl.start[b]);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -581,7 +593,7 @@ unsigned grid_for(size_t items, unsigned cap)
 
 }  // namespace
 
-int rmse_blocks(int m) { return (m + kRmseSignals - 1) / kRmseSignals; }
+int rmse_blocks(int m) { return rmse_blocks_dev(m); }
 
 int max_chunks(const dl_params &prm)
 {
