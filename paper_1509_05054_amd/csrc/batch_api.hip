@@ -401,8 +401,7 @@ dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void
             DL_TRY(launch_batched_omp(omp + par + S.first, list(S.list, S.num), S.items, S.sh.lps,
                                       S.sh.npl, S.sh.smax, st));
         DL_TRY(launch_batched_csr(csr, list(P.l_count, count), P.n_count, list(P.l_quad, count),
-                                  P.n_quad, list(P.l_one, count), list(P.l_scatter, count),
-                                  P.n_scatter, P.max_n, st));
+                                  P.n_quad, list(P.l_scatter, count), P.n_scatter, P.max_n, st));
         DL_TRY(launch_batched_update(upd + par, list(P.l_chunk, count), P.n_chunk, st));
         DL_TRY(launch_batched_rmse(rmse + par, list(P.l_rmse, count), P.n_rmse,
                                    list(P.l_one, count), k, st));

@@ -9,9 +9,11 @@
 //             the chunks.  Result: per-(atom, block) counts and, per entry,
 //             its rank among the block's uses of the atom.
 //   scan    : one wave per atom scans its per-block counts into offsets and
-//             its total; a one-workgroup launch then scans the atom totals
-//             into row_ptr (and chunk_ptr, the update's chunks of kChunk users).
-//   scatter : one thread per entry: users[row_ptr + offset + rank] = entry.
+//             its total.
+//   scatter : every workgroup scans the atom totals into atom offsets in LDS
+//             (the first also writes row_ptr and chunk_ptr, the update's
+//             chunks of kChunk users); one thread per entry:
+//             users[row offset + block offset + rank] = entry.
 // Entries of an atom end up in increasing (signal, slot) order, so the
 // result is unique and the atom update's summation order is fixed.
 #include "dl_internal.h"
@@ -141,13 +143,13 @@ __device__ inline void csr_scan_body(int32_t *__restrict__ blkcnt, int32_t *__re
         tot[a] = carry;
 }
 
-// Exclusive scan of the atom totals into row_ptr, and of their chunk counts
-// (kChunk users per chunk) into chunk_ptr; one workgroup, thread t owning
-// atoms [t*per, (t+1)*per).  A launch of its own after the per-atom scan, so
-// the totals need no device-scope fence.
-__device__ inline void csr_total_body(const int32_t *__restrict__ tot,
-                                      int32_t *__restrict__ row_ptr,
-                                      int32_t *__restrict__ chunk_ptr, int n)
+// Exclusive scan of the atom totals into sRow[0..n] (users) and, when
+// chunk_ptr is given, of their chunk counts (kChunk users per chunk) into
+// chunk_ptr, and sRow into row_ptr; 256 threads, thread t owning atoms
+// [t*per, (t+1)*per).
+__device__ inline void csr_prefix_block(const int32_t *__restrict__ tot, int n, int32_t *sRow,
+                                        int32_t *__restrict__ row_ptr,
+                                        int32_t *__restrict__ chunk_ptr)
 {
     __shared__ int sh[2][4];
     const int lane = threadIdx.x & 63;
@@ -165,6 +167,7 @@ __device__ inline void csr_total_body(const int32_t *__restrict__ tot,
     }
     const int xu = wave_inclusive_scan(su);
     const int xc = wave_inclusive_scan(sc);
+    __syncthreads();  // sh and sRow of a previous item are no longer read
     if (lane == 63) {
         sh[0][wave] = xu;
         sh[1][wave] = xc;
@@ -184,17 +187,23 @@ __device__ inline void csr_total_body(const int32_t *__restrict__ tot,
         const int aa = a0 + q;
         if (aa < n) {
             const int v = tot[aa];
-            row_ptr[aa] = ru;
-            chunk_ptr[aa] = rc;
+            sRow[aa] = ru;
+            if (chunk_ptr) {
+                row_ptr[aa] = ru;
+                chunk_ptr[aa] = rc;
+            }
             ru += v;
             rc += (v + kChunk - 1) / kChunk;
         }
     }
     if (threadIdx.x == 0) {
-        row_ptr[n] = tu;
-        chunk_ptr[n] = tc;
+        sRow[n] = tu;
+        if (chunk_ptr) {
+            row_ptr[n] = tu;
+            chunk_ptr[n] = tc;
+        }
     }
-    __syncthreads();  // sh is reused by the next item of a persistent workgroup
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blkcnt,
@@ -203,20 +212,21 @@ __global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blk
     csr_scan_body(blkcnt, tot, n, nb, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void csr_total_kernel(const int32_t *__restrict__ tot,
-                                                        int32_t *__restrict__ row_ptr,
-                                                        int32_t *__restrict__ chunk_ptr, int n)
-{
-    csr_total_body(tot, row_ptr, chunk_ptr, n);
-}
 
+// Scatter (workgroup of 256 threads): the atom offsets are scanned from the
+// atom totals by every workgroup (n <= 1024, cheap), and item 0 also writes
+// row_ptr and chunk_ptr for the atom update.
 __device__ inline void csr_scatter_body(const int32_t *__restrict__ idx,
                                         const int32_t *__restrict__ blkoff,
-                                        const int32_t *__restrict__ row_ptr,
+                                        const int32_t *__restrict__ tot,
+                                        int32_t *__restrict__ row_ptr,
+                                        int32_t *__restrict__ chunk_ptr,
                                         const int32_t *__restrict__ lrank,
                                         int32_t *__restrict__ users, float *__restrict__ val_pad,
                                         int n, int m, int s, int nb, int blk, int nblk)
 {
+    __shared__ int32_t sRow[1025];
+    csr_prefix_block(tot, n, sRow, row_ptr, blk == 0 ? chunk_ptr : nullptr);
     const size_t total = (size_t)m * s;
     for (size_t pos = (size_t)blk * blockDim.x + threadIdx.x; pos < total;
          pos += (size_t)nblk * blockDim.x) {
@@ -227,18 +237,18 @@ __device__ inline void csr_scatter_body(const int32_t *__restrict__ idx,
             continue;
         }
         const int b = (int)(pos / s) / kCsrBlock;
-        users[row_ptr[atom] + blkoff[(size_t)atom * nb + b] + lrank[pos]] = (int32_t)pos;
+        users[sRow[atom] + blkoff[(size_t)atom * nb + b] + lrank[pos]] = (int32_t)pos;
     }
 }
 
-__global__ void csr_scatter_kernel(const int32_t *__restrict__ idx,
-                                   const int32_t *__restrict__ blkoff,
-                                   const int32_t *__restrict__ row_ptr,
-                                   const int32_t *__restrict__ lrank, int32_t *__restrict__ users,
-                                   float *__restrict__ val_pad, int n, int m, int s, int nb)
+__global__ __launch_bounds__(256) void csr_scatter_kernel(
+    const int32_t *__restrict__ idx, const int32_t *__restrict__ blkoff,
+    const int32_t *__restrict__ tot, int32_t *__restrict__ row_ptr,
+    int32_t *__restrict__ chunk_ptr, const int32_t *__restrict__ lrank,
+    int32_t *__restrict__ users, float *__restrict__ val_pad, int n, int m, int s, int nb)
 {
-    csr_scatter_body(idx, blkoff, row_ptr, lrank, users, val_pad, n, m, s, nb, blockIdx.x,
-                     gridDim.x);
+    csr_scatter_body(idx, blkoff, tot, row_ptr, chunk_ptr, lrank, users, val_pad, n, m, s, nb,
+                     blockIdx.x, gridDim.x);
 }
 
 // ---- batched problems: one launch per pass over every problem's items ----
@@ -280,24 +290,6 @@ __global__ __launch_bounds__(256) void csr_scan_batched(const CsrArgs *__restric
         batch_leave(bl.q, gridDim.x);
 }
 
-// One item per problem.
-__global__ __launch_bounds__(256) void csr_total_batched(const CsrArgs *__restrict__ tab,
-                                                         BatchList bl)
-{
-    __shared__ int slot;
-    const int total = bl.start[bl.count];
-    for (;;) {
-        const int it = batch_next_item(bl.q, &slot);
-        if (it >= total)
-            break;
-        const int b = batch_find(bl.start, bl.count, it);
-        const CsrArgs a = tab[b];
-        csr_total_body(a.tot, a.row_ptr, a.chunk_ptr, a.n);
-    }
-    if (threadIdx.x == 0)
-        batch_leave(bl.q, gridDim.x);
-}
-
 __global__ __launch_bounds__(256) void csr_scatter_batched(const CsrArgs *__restrict__ tab,
                                                            BatchList bl)
 {
@@ -309,8 +301,9 @@ __global__ __launch_bounds__(256) void csr_scatter_batched(const CsrArgs *__rest
             break;
         const int b = batch_find(bl.start, bl.count, it);
         const CsrArgs a = tab[b];
-        csr_scatter_body(a.idx, a.blkcnt, a.row_ptr, a.lrank, a.users, a.val_pad, a.n, a.m, a.s,
-                         csr_nb(a.m), it - bl.start[b], bl.start[b + 1] - bl.start[b]);
+        csr_scatter_body(a.idx, a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.lrank, a.users,
+                         a.val_pad, a.n, a.m, a.s, csr_nb(a.m), it - bl.start[b],
+                         bl.start[b + 1] - bl.start[b]);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -323,8 +316,8 @@ int csr_blocks(int m) { return (m + kCsrBlock - 1) / kCsrBlock; }
 // Items: count = signal blocks, scan = atom quads, scatter = blocks of 256 entries.
 hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, int count_items,
                               const BatchList &scan_list, int scan_items,
-                              const BatchList &total_list, const BatchList &scatter_list,
-                              int scatter_items, int max_n, hipStream_t st)
+                              const BatchList &scatter_list, int scatter_items, int max_n,
+                              hipStream_t st)
 {
     const size_t shmem = (sizeof(unsigned long long) + sizeof(int32_t)) * kWavesPerBlock * max_n;
     int wg = batch_workers((const void *)csr_count_batched, kCsrBlock, shmem, count_items);
@@ -337,10 +330,6 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
     wg = batch_workers((const void *)csr_scan_batched, 256, 0, scan_items);
     prof_begin(DL_K_CSR_SCAN, st);
     hipLaunchKernelGGL(csr_scan_batched, dim3(wg), dim3(256), 0, st, tab, scan_list);
-    if ((e = hipGetLastError()) != hipSuccess)
-        return e;
-    wg = batch_workers((const void *)csr_total_batched, 256, 0, total_list.count);
-    hipLaunchKernelGGL(csr_total_batched, dim3(wg), dim3(256), 0, st, tab, total_list);
     prof_end(DL_K_CSR_SCAN, st);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
@@ -365,8 +354,6 @@ hipError_t launch_csr(const CsrArgs &a, hipStream_t st)
     prof_begin(DL_K_CSR_SCAN, st);
     hipLaunchKernelGGL(csr_scan_kernel, dim3((a.n + 3) / 4), dim3(256), 0, st, a.blkcnt, a.tot,
                        a.n, nb);
-    hipLaunchKernelGGL(csr_total_kernel, dim3(1), dim3(256), 0, st, a.tot, a.row_ptr,
-                       a.chunk_ptr, a.n);
     prof_end(DL_K_CSR_SCAN, st);
     e = hipGetLastError();
     if (e != hipSuccess)
@@ -377,7 +364,8 @@ hipError_t launch_csr(const CsrArgs &a, hipStream_t st)
         blocks = 8192;
     prof_begin(DL_K_CSR_SCATTER, st);
     hipLaunchKernelGGL(csr_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a.idx,
-                       a.blkcnt, a.row_ptr, a.lrank, a.users, a.val_pad, a.n, a.m, a.s, nb);
+                       a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.lrank, a.users, a.val_pad, a.n,
+                       a.m, a.s, nb);
     prof_end(DL_K_CSR_SCATTER, st);
     return hipGetLastError();
 }

@@ -282,8 +282,8 @@ hipError_t launch_batched_omp(const OmpArgs *tab, const BatchList &bl, int items
                               int npl, int smax, hipStream_t st);
 hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, int count_items,
                               const BatchList &scan_list, int scan_items,
-                              const BatchList &total_list, const BatchList &scatter_list,
-                              int scatter_items, int max_n, hipStream_t st);
+                              const BatchList &scatter_list, int scatter_items, int max_n,
+                              hipStream_t st);
 hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
                                  int chunk_items, hipStream_t st);
 hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items,
