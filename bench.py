@@ -374,6 +374,9 @@ def main():
                          "the reference for scaling HBM counters")
     ap.add_argument("--row-only", default=None,
                     help="measure only this row (precision, learned or batched) and print it")
+    ap.add_argument("--omp-only", action="store_true",
+                    help="run the coding stage (dl_omp) twice on the workload and stop (for "
+                         "counter profiles of the OMP kernel)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -399,6 +402,19 @@ def main():
         print(json.dumps({args.row_only: fn()}))
         return
     w = synth.workload(args.workload)
+    if args.omp_only:
+        prec = args.precision or ("bf16" if args.workload.startswith("patches_p256") else "fp32")
+        prm = dl.Params(w.p, w.n, w.m, w.s,
+                        precision=dl.PREC_BF16 if prec == "bf16" else dl.PREC_FP32)
+        ws = dl.workspace(prm)
+        Yd, Dd = g.dev(w.Y), g.dev(w.D0)
+        idx = torch.empty((w.m, w.s), dtype=torch.int32, device="cuda:0")
+        val = torch.empty((w.m, w.s), device="cuda:0")
+        for _ in range(2):
+            dl.omp(prm, Dd, Yd, idx, val, ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": args.workload, "omp_runs": 2}))
+        return
     iters = args.iters or w.iters
     gs = args.group_size or w.n
     precision = args.precision or ("bf16" if args.workload.startswith("patches_p256") else "fp32")
