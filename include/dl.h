@@ -227,8 +227,8 @@ typedef enum {
     DL_K_CSR_SCAN,      /* users of every atom: offsets */
     DL_K_CSR_SCATTER,   /* users of every atom: placement */
     DL_K_UPD_PASS1,     /* F x^T per chunk of users */
-    DL_K_UPD_REDUCE,    /* sum over chunks and normalisation */
-    DL_K_UPD_PASS2,     /* AK-SVD refresh of X */
+    DL_K_UPD_REDUCE,    /* (reserved: the sum over chunks runs inside pass 2) */
+    DL_K_UPD_PASS2,     /* sum over chunks, normalisation, AK-SVD refresh of X */
     DL_K_UPD_EUPDATE,   /* error update between groups */
     DL_K_RMSE,          /* error with the FP64 reduction */
     DL_K_MISC,          /* casts, copies, normalisation, residual */

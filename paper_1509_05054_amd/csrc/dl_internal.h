@@ -25,9 +25,7 @@ struct Control {
     unsigned long long zero_updates;
     unsigned long long nonfinite;
     unsigned long long fallbacks;
-    unsigned int rmse_done;  // (unused)
-    unsigned int csr_done;   // (unused)
-    unsigned int pad[14];
+    unsigned int pad[16];
 };
 
 // Byte offsets of the workspace regions (each 256-byte aligned).

@@ -223,6 +223,31 @@ def test_update_matches_oracle(name, p, n, s, m, gs):
     assert abs(rg - rr) / rr < 1e-4, (rg, rr)
 
 
+@pytest.mark.parametrize("gs", [64, 10])
+def test_update_unused_and_zero_atoms(gs):
+    """Atoms no signal uses keep their value (and are counted); an atom whose
+    users all carry a zero coefficient has F x^T = 0 and keeps its value too;
+    the rest follows the oracle."""
+    note(f"update unused / zero atoms gs={gs}")
+    p, n, s, m = 16, 64, 3, 900
+    rng = np.random.default_rng(21)
+    D = rng.standard_normal((n, p))
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    Y = rng.standard_normal((m, p)).astype(np.float32)
+    idx = np.stack([rng.choice(n // 2, size=s, replace=False) for _ in range(m)]).astype(np.int32)
+    val = rng.standard_normal((m, s)).astype(np.float32)
+    val[idx == 5] = 0.0  # atom 5: users, all with zero coefficients
+    Dr, vnr, unused = oracle.jau_update(Y, D, idx, val, gs)
+    Dg, vng, st = gpu_update(Y, D, idx, val, gs)
+    assert unused == n // 2 and st["unused_atoms"] == unused
+    assert st["zero_updates"] == 1
+    np.testing.assert_array_equal(Dg[n // 2:], D[n // 2:].astype(np.float64))
+    np.testing.assert_array_equal(Dg[5], D[5].astype(np.float64))
+    assert np.abs(Dg - Dr).max() < 1e-4
+    ynorm = np.linalg.norm(Y.astype(np.float64), axis=1, keepdims=True)
+    assert (np.abs(vng - vnr) / ynorm).max() < 1e-4
+
+
 def test_update_sgk_rule_keeps_x_and_matches_aksvd_atoms():
     note("update sgk")
     Y, D = _patch_problem(64, 128, 4000, seed=5)
@@ -234,13 +259,24 @@ def test_update_sgk_rule_keeps_x_and_matches_aksvd_atoms():
     assert np.abs(Da - Ds).max() < 1e-6
 
 
-def test_rmse_matches_oracle():
-    note("rmse")
-    Y, D = _patch_problem(64, 256, 5000, seed=9)
-    ir, vr, _ = oracle.omp(D, Y, 6)
-    v32 = vr.astype(np.float32)
-    rg = gpu_rmse(Y, D, ir, v32)
-    rr = oracle.rmse(Y, D, ir, v32)
+@pytest.mark.parametrize("p,n,s,m", [
+    (64, 256, 6, 5000),     # fewer signal blocks than the workgroup cap
+    (64, 256, 6, 40001),    # more than 1024 x 16 signals: workgroups stride, ragged tail
+    (256, 1024, 12, 3001),  # several lane-group rounds per block
+    (36, 72, 5, 777),       # p not a power of two
+])
+def test_rmse_matches_oracle(p, n, s, m):
+    note(f"rmse p={p} n={n} s={s} m={m}")
+    rng = np.random.default_rng(9 + m)
+    Y = rng.standard_normal((m, p)).astype(np.float32)
+    D = rng.standard_normal((n, p))
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    idx = np.stack([rng.choice(n, size=s, replace=False) for _ in range(m)]).astype(np.int32)
+    val = rng.standard_normal((m, s)).astype(np.float32)
+    idx[::7, -1] = -1  # unused slots
+    val[::7, -1] = 0.0
+    rg = gpu_rmse(Y, D, idx, val)
+    rr = oracle.rmse(Y, D, idx, val)
     assert abs(rg - rr) / rr < 1e-6, (rg, rr)
 
 
