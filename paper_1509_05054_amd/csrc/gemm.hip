@@ -145,17 +145,20 @@ __device__ inline void gemm_f32_tile(const GemmF32 &P, int brow0, int bcol0)
     store_block<TM, 32 * TM>(P.C, M, N, P.ldc, brow0, bcol0, acc, sC);
 }
 
-// FP32 products use workgroup tiles of kF32M rows (64: measured faster than
-// 32 on the short-K products, K = p).
+// FP32 products use workgroup tiles of 32 TM rows: TM = 2 (64 rows) for the
+// batched and smaller products, TM = 4 (128 rows) once the products have
+// many rows (measured: 64 rows faster at m = 16384, 128 rows at m = 262144).
 constexpr int kF32TM = 2;
 constexpr int kF32M = 32 * kF32TM;
+constexpr int kTallRows = 65536;
 
+template <int TM>
 __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1, int tiles_y0)
 {
     GemmF32 P;
     int brow0, bcol0;
-    if (pick_problem(p0, p1, tiles_y0, P, brow0, bcol0, kF32M))
-        gemm_f32_tile<kF32TM>(P, brow0, bcol0);
+    if (pick_problem(p0, p1, tiles_y0, P, brow0, bcol0, 32 * TM))
+        gemm_f32_tile<TM>(P, brow0, bcol0);
 }
 
 __host__ __device__ inline int gemm_tiles(const GemmF32 &P)
@@ -203,11 +206,13 @@ __device__ inline u16x8 load_bf16x8(const uint16_t *ptr, int k, int K)
     return v;
 }
 
+template <int TM>
 __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmBF16 p0, GemmBF16 p1, int tiles_y0)
 {
+    constexpr int kTM = TM;
     GemmBF16 P;
     int brow0, bcol0;
-    if (!pick_problem(p0, p1, tiles_y0, P, brow0, bcol0))
+    if (!pick_problem(p0, p1, tiles_y0, P, brow0, bcol0, 32 * TM))
         return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -247,8 +252,8 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmBF16 p0, GemmBF16
                     __builtin_bit_cast(bf16x8, av[a]), __builtin_bit_cast(bf16x8, bv[b]),
                     acc[a][b], 0, 0, 0);
     }
-    __shared__ float sC[kBlockM * kStageLd];
-    store_block<kTM, kBlockM>(P.C, M, N, P.ldc, brow0, bcol0, acc, sC);
+    __shared__ float sC[32 * TM * kStageLd];
+    store_block<TM, 32 * TM>(P.C, M, N, P.ldc, brow0, bcol0, acc, sC);
 }
 
 // Round-to-nearest-even FP32 -> BF16 on the bit pattern (NaN kept quiet).
@@ -288,12 +293,18 @@ hipError_t launch_grouped(Kern kern, const P &p0, const P *p1, int kid, hipStrea
 
 hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st)
 {
-    return launch_grouped(gemm_nt_f32_kernel, p0, p1, kid, st, kF32M);
+    const int rows = p0.M > (p1 ? p1->M : 0) ? p0.M : p1->M;
+    if (rows >= kTallRows)
+        return launch_grouped(gemm_nt_f32_kernel<4>, p0, p1, kid, st, 128);
+    return launch_grouped(gemm_nt_f32_kernel<kF32TM>, p0, p1, kid, st, kF32M);
 }
 
 hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st)
 {
-    return launch_grouped(gemm_nt_bf16_kernel, p0, p1, kid, st);
+    const int rows = p0.M > (p1 ? p1->M : 0) ? p0.M : p1->M;
+    if (rows >= kTallRows)
+        return launch_grouped(gemm_nt_bf16_kernel<4>, p0, p1, kid, st, 128);
+    return launch_grouped(gemm_nt_bf16_kernel<2>, p0, p1, kid, st, 64);
 }
 
 int gemm_pair_items(const GemmPair &pp) { return gemm_tiles(pp.g) + gemm_tiles(pp.c); }
