@@ -20,7 +20,8 @@ Prints one JSON line:
                           30 steady-state iterations timed on both paths
                batched    64 uneven problems, 20 iterations, one persistent
                           launch per stage, default and autotuned OMP shapes,
-                          against the problems run one after another
+                          against the problems run one after another; and
+                          200 small problems the same way
 """
 import argparse
 import hashlib
@@ -336,6 +337,40 @@ def row_batched(g, steps):
             totals[k] = (b, ta + a * iters, u)
     dom, rl = roofline(prof, totals, "fp32")
     r_final = np.array([float(pb.rmse[-1].item()) for pb in probs])
+
+    # many small problems (the shape of the dictionary-recovery experiment,
+    # p=20 n=50 m=1500 s=3..5), where one launch per stage matters most
+    small = []
+    for b in range(200):
+        sb = 3 + b % 3
+        Ys, _, _, _ = synth.recovery_problem(20, 50, sb, 1500, 0.0, seed=9000 + b, snr_db=20)
+        D0s_ = synth.initial_dictionary(Ys, 50, seed=9500 + b)
+        small.append(dl.Problem(dl.Params(20, 50, 1500, sb), g.dev(Ys), g.dev(D0s_),
+                                torch.empty((1500, sb), dtype=torch.int32, device="cuda:0"),
+                                torch.empty((1500, sb), device="cuda:0"),
+                                torch.empty(iters, dtype=torch.float64, device="cuda:0")))
+    small_D0 = [pb.D.clone() for pb in small]
+    small_ws = dl.batch_workspace(small)
+    small_single = [dl.workspace(pb.prm) for pb in small]
+
+    def small_reset():
+        for pb, d0 in zip(small, small_D0):
+            pb.D.copy_(d0)
+
+    def small_batched():
+        small_reset()
+        dl.iterate_batched(small, iters, small_ws)
+
+    def small_sequential():
+        small_reset()
+        for pb, w1 in zip(small, small_single):
+            dl.iterate(pb.prm, pb.Y, pb.D, iters, pb.X_idx, pb.X_val, pb.rmse, w1)
+
+    small_batched()
+    small_sequential()
+    t_sb = g.time_ms(lambda: [small_batched() for _ in range(steps)]) / steps
+    t_ss = g.time_ms(lambda: [small_sequential() for _ in range(steps)]) / steps
+    small_total = 200 * 1500 * iters
     return {
         "workload": "64 uneven problems: p in {16,36,64,144,256}, n in {2p,4p}, s in 3..16, "
                     "m log-uniform 2k..64k (seed 505)",
@@ -349,6 +384,11 @@ def row_batched(g, steps):
                                        for q, (lps, npl) in zip(specs, shapes))),
         "roofline": rl, "rmse_final_mean": float(r_final.mean()),
         "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+        "small_problems": {
+            "workload": "200 problems p=20 n=50 m=1500 s=3..5, 20 iterations",
+            "value_batched": small_total / (t_sb / 1e3),
+            "value_sequential_single_calls": small_total / (t_ss / 1e3),
+            "batched_over_sequential": t_ss / t_sb, "ms_batched": t_sb, "ms_sequential": t_ss},
     }
 
 
