@@ -123,9 +123,14 @@ dl_status check_ws(const dl_params *prm, const void *ws, size_t ws_bytes, Ws *ou
 
 // G and A0 for the coding stage in one launch, in the precision the
 // parameters ask for; rows of G and A0 have stride ldn.
+// prev_err: optional error partials of the previous iteration, computed by
+// extra workgroups of the grouped launch (independent of the products).
 dl_status products(const dl_params &prm, const float *D, const float *Y, float *G, float *A0,
-                   const Ws *ws, hipStream_t st, int ldn, const int32_t *m_dev = nullptr)
+                   const Ws *ws, hipStream_t st, int ldn, const int32_t *m_dev = nullptr,
+                   const RmseArgs *prev_err = nullptr)
 {
+    if (prev_err && !(G && A0))
+        return DL_EINVAL;
     if (prm.precision == DL_PREC_BF16) {
         uint16_t *Dbf = ws->at<uint16_t>(ws->L.Dbf);
         uint16_t *Ybf = ws->at<uint16_t>(ws->L.Ybf);
@@ -134,7 +139,7 @@ dl_status products(const dl_params &prm, const float *D, const float *Y, float *
         const GemmBF16 g{Dbf, Dbf, G, prm.n, prm.n, prm.p, ldn, nullptr};
         const GemmBF16 c{Ybf, Dbf, A0, prm.m, prm.n, prm.p, ldn, m_dev};
         if (G && A0)
-            DL_TRY(launch_gemm_nt_bf16(g, &c, DL_K_CORR, st));
+            DL_TRY(launch_gemm_nt_bf16(g, &c, DL_K_CORR, st, prev_err));
         else if (G)
             DL_TRY(launch_gemm_nt_bf16(g, nullptr, DL_K_GRAM, st));
         else if (A0)
@@ -143,7 +148,7 @@ dl_status products(const dl_params &prm, const float *D, const float *Y, float *
         const GemmF32 g{D, D, G, prm.n, prm.n, prm.p, ldn, nullptr};
         const GemmF32 c{Y, D, A0, prm.m, prm.n, prm.p, ldn, m_dev};
         if (G && A0)
-            DL_TRY(launch_gemm_nt_f32(g, &c, DL_K_CORR, st));
+            DL_TRY(launch_gemm_nt_f32(g, &c, DL_K_CORR, st, prev_err));
         else if (G)
             DL_TRY(launch_gemm_nt_f32(g, nullptr, DL_K_GRAM, st));
         else if (A0)
@@ -158,6 +163,7 @@ struct OmpExtra {
     const int32_t *rowmap = nullptr;
     float *rnorm = nullptr;
     bool products = true;          // form G and A0 here
+    const RmseArgs *prev_err = nullptr;  // error partials carried by the products launch
 };
 
 dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t *idx, float *val,
@@ -167,10 +173,13 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
     float *A0 = ws.at<float>(ws.L.A0);
     const float *Yin = x.Y ? x.Y : Y;
     if (x.products) {
-        dl_status rc = products(prm, D, Yin, G, A0, &ws, st, padded_n(prm.n));
+        dl_status rc = products(prm, D, Yin, G, A0, &ws, st, padded_n(prm.n), nullptr,
+                                x.prev_err);
         if (rc != DL_OK)
             return rc;
     }
+    if (x.prev_err && !x.products)
+        return DL_EINVAL;
     OmpArgs a;
     a.A0 = A0;
     a.G = G;
@@ -197,8 +206,10 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
     return DL_OK;
 }
 
+// prev_err: optional error whose partials are complete; its final sum is
+// carried by the scan launch.
 dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, int32_t *users,
-                  float *val_pad, const Ws &ws, hipStream_t st)
+                  float *val_pad, const Ws &ws, hipStream_t st, const RmseArgs *prev_err = nullptr)
 {
     CsrArgs c;
     c.idx = idx;
@@ -213,7 +224,7 @@ dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, in
     c.n = prm.n;
     c.m = prm.m;
     c.s = prm.s;
-    DL_TRY(launch_csr(c, st));
+    DL_TRY(launch_csr(c, st, prev_err));
     return DL_OK;
 }
 
@@ -221,11 +232,11 @@ dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, in
 // Y - D X on entry.
 dl_status run_update(const dl_params &prm, const float *Y, const float *D, float *Dn,
                      const int32_t *idx, const float *val, float *valn, const Ws &ws,
-                     hipStream_t st)
+                     hipStream_t st, const RmseArgs *prev_err = nullptr)
 {
     int32_t *row_ptr = ws.at<int32_t>(ws.L.row_ptr);
     int32_t *users = ws.at<int32_t>(ws.L.users);
-    dl_status rc = run_csr(prm, idx, row_ptr, users, valn, ws, st);
+    dl_status rc = run_csr(prm, idx, row_ptr, users, valn, ws, st, prev_err);
     if (rc != DL_OK)
         return rc;
     UpdateArgs u;
@@ -253,8 +264,8 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
     return DL_OK;
 }
 
-dl_status run_rmse(const dl_params &prm, const float *Y, const float *D, const int32_t *idx,
-                   const float *val, double *out, const Ws &ws, hipStream_t st)
+RmseArgs rmse_args(const dl_params &prm, const float *Y, const float *D, const int32_t *idx,
+                   const float *val, double *out, const Ws &ws)
 {
     RmseArgs r;
     r.Y = Y;
@@ -268,7 +279,13 @@ dl_status run_rmse(const dl_params &prm, const float *Y, const float *D, const i
     r.n = prm.n;
     r.m = prm.m;
     r.s = prm.s;
-    DL_TRY(launch_rmse(r, st));
+    return r;
+}
+
+dl_status run_rmse(const dl_params &prm, const float *Y, const float *D, const int32_t *idx,
+                   const float *val, double *out, const Ws &ws, hipStream_t st)
+{
+    DL_TRY(launch_rmse(rmse_args(prm, Y, D, idx, val, out, ws), st));
     return DL_OK;
 }
 
@@ -448,24 +465,40 @@ static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, in
     // the dictionary alternates between the caller's buffer and the workspace
     float *Dcur = D, *Dnext = Dws;
     const size_t ms = (size_t)q.m * q.s;
+    // The error of iteration k needs only its outputs (Dn, X), which nothing
+    // before iteration k+1's coding overwrites.  For signal counts whose
+    // error partials take one signal block per workgroup (latency-bound
+    // sizes), its partials run as extra workgroups of k+1's products launch
+    // and its final sum in k+1's CSR scan launch: two launches fewer per
+    // iteration, with the same bodies and block decomposition as the error
+    // launches, so the same bits.  Larger counts (each partial workgroup
+    // striding over several blocks) keep the error launches, which measured
+    // faster there.  The last iteration's deferred error runs on its own.
+    const bool defer = error_defer_ok(q.m);
+    RmseArgs prev{};
+    bool pending = false;
     for (int k = 0; k < iters; ++k) {
         OmpExtra x;
         x.rnorm = rref;
+        x.prev_err = pending ? &prev : nullptr;
         rc = run_omp(q, Dcur, Y, X_idx, val_ws, w, st, x);
         if (rc != DL_OK)
             return rc;
         if (hist)
             DL_TRY(launch_copy(X_idx, hist + (size_t)k * ms, 4 * ms, st));
-        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st);
+        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st, pending ? &prev : nullptr);
         if (rc != DL_OK)
             return rc;
-        rc = run_rmse(q, Y, Dnext, X_idx, X_val, rmse + k, w, st);
-        if (rc != DL_OK)
-            return rc;
+        prev = rmse_args(q, Y, Dnext, X_idx, X_val, rmse + k, w);
+        pending = defer;
+        if (!defer)
+            DL_TRY(launch_rmse(prev, st));
         float *t = Dcur;
         Dcur = Dnext;
         Dnext = t;
     }
+    if (pending)
+        DL_TRY(launch_rmse(prev, st));
     if (Dcur != D)
         DL_TRY(launch_copy(Dcur, D, sizeof(float) * (size_t)q.n * q.p, st));
     return DL_OK;

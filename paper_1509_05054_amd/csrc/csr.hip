@@ -17,6 +17,7 @@
 // Entries of an atom end up in increasing (signal, slot) order, so the
 // result is unique and the atom update's summation order is fixed.
 #include "dl_internal.h"
+#include "rmse_body.h"
 
 namespace dlk {
 namespace {
@@ -206,9 +207,16 @@ __device__ inline void csr_prefix_block(const int32_t *__restrict__ tot, int n, 
     __syncthreads();
 }
 
+// The last workgroup, when err_blocks > 0, sums the partials of an error
+// (independent of the scan).
 __global__ __launch_bounds__(256) void csr_scan_kernel(int32_t *__restrict__ blkcnt,
-                                                       int32_t *__restrict__ tot, int n, int nb)
+                                                       int32_t *__restrict__ tot, int n, int nb,
+                                                       RmseArgs err, int err_blocks)
 {
+    if (err_blocks > 0 && blockIdx.x == gridDim.x - 1) {
+        rmse_final_body(err, err_blocks);
+        return;
+    }
     csr_scan_body(blkcnt, tot, n, nb, blockIdx.x);
 }
 
@@ -340,7 +348,7 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
     return hipGetLastError();
 }
 
-hipError_t launch_csr(const CsrArgs &a, hipStream_t st)
+hipError_t launch_csr(const CsrArgs &a, hipStream_t st, const RmseArgs *err)
 {
     const int nb = csr_blocks(a.m);
     const size_t shmem = (sizeof(unsigned long long) + sizeof(int32_t)) * kWavesPerBlock * a.n;
@@ -352,8 +360,9 @@ hipError_t launch_csr(const CsrArgs &a, hipStream_t st)
     if (e != hipSuccess)
         return e;
     prof_begin(DL_K_CSR_SCAN, st);
-    hipLaunchKernelGGL(csr_scan_kernel, dim3((a.n + 3) / 4), dim3(256), 0, st, a.blkcnt, a.tot,
-                       a.n, nb);
+    const int eb = err ? rmse_blocks_dev(err->m) : 0;
+    hipLaunchKernelGGL(csr_scan_kernel, dim3((a.n + 3) / 4 + (err ? 1 : 0)), dim3(256), 0, st,
+                       a.blkcnt, a.tot, a.n, nb, err ? *err : RmseArgs{}, eb);
     prof_end(DL_K_CSR_SCAN, st);
     e = hipGetLastError();
     if (e != hipSuccess)

@@ -76,8 +76,13 @@ struct GemmBF16 {  // BF16 inputs as uint16 bit patterns
     int M, N, K, ldc;
     const int32_t *M_dev;
 };
-hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st);
-hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st);
+struct RmseArgs;
+// err: optional error partials (rmse_blocks(err->m) workgroups of the
+// error's partial pass) run by extra workgroups of the same launch.
+hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st,
+                              const RmseArgs *err = nullptr);
+hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st,
+                               const RmseArgs *err = nullptr);
 // Round FP32 to BF16 (nearest even).
 hipError_t launch_cast_bf16(const float *x, uint16_t *y, size_t count, hipStream_t st);
 
@@ -117,7 +122,9 @@ struct CsrArgs {
     float *val_pad;      // optional: zero written at padding slots
     int n, m, s;
 };
-hipError_t launch_csr(const CsrArgs &a, hipStream_t st);
+// err: optional error whose partials are complete; its final sum runs as one
+// extra workgroup of the scan launch.
+hipError_t launch_csr(const CsrArgs &a, hipStream_t st, const RmseArgs *err = nullptr);
 
 struct UpdateArgs {
     const float *Y;       // [m][p]
@@ -145,6 +152,9 @@ struct RmseArgs {
     int p, n, m, s;
 };
 hipError_t launch_rmse(const RmseArgs &a, hipStream_t st);
+// Whether an error over m signals is one signal block per partial workgroup
+// (the sizes at which it is carried by the next iteration's launches).
+bool error_defer_ok(int m);
 
 // E = Y - D X (one signal per lane group).
 hipError_t launch_residual(const float *Y, const float *D, const int32_t *idx, const float *val,

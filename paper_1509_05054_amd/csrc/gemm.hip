@@ -12,11 +12,11 @@
 // holds is irrelevant to the product as long as A and B use the same choice,
 // so every lane loads 4 (FP32) or 8 (BF16) consecutive K values at once.
 #include "dl_internal.h"
+#include "rmse_body.h"
 
 namespace dlk {
 namespace {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
@@ -71,13 +71,59 @@ __device__ inline void store_block(float *C, int M, int N, int ldc, int brow0, i
     __syncthreads();  // sC is reused by the next tile of a persistent workgroup
 }
 
+// Direct stores for products computed with the operands swapped (the MFMA
+// gets B as its first operand): lane l then holds C[l%16][4*(l/16) + r] of
+// each 16x16 tile, four consecutive columns, written as one 16-byte store.
+template <int TM>
+__device__ inline void store_direct(float *C, int M, int N, int ldc, int row0, int col0,
+                                    const f32x4 (&acc)[TM][kTN])
+{
+    const int lane = threadIdx.x & 63;
+    const bool vec_ok = (ldc % 4) == 0 && ((uintptr_t)C % 16) == 0;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+        const int row = row0 + 16 * a + (lane & 15);
+        if (row >= M)
+            continue;
+#pragma unroll
+        for (int b = 0; b < kTN; ++b) {
+            const int col = col0 + 16 * b + 4 * (lane >> 4);
+            float *dst = C + (size_t)row * ldc + col;
+            if (vec_ok && col + 3 < N) {
+                *reinterpret_cast<f32x4 *>(dst) = acc[a][b];
+            } else {
+                for (int q = 0; q < 4 && col + q < N; ++q)
+                    dst[q] = acc[a][b][q];
+            }
+        }
+    }
+}
+
+// The grid is one-dimensional (row tiles may exceed the 65535 limit of the
+// y dimension): workgroup t < tiles computes tile (t % tiles_x, t / tiles_x)
+// of the grid of output tiles, row-major as a two-dimensional launch would
+// order them.  The err_blocks workgroups after the tiles carry the partial
+// pass of an error (measured: faster behind the tiles than ahead of them).
+// Returns the tile index, or -1 for the error workgroups after running their
+// share.
+__device__ inline int error_blocks(int tiles, const RmseArgs &err, int err_blocks)
+{
+    const int w = (int)blockIdx.x;
+    if (w < tiles)
+        return w;
+    if (w - tiles < err_blocks)
+        rmse_body(err, w - tiles, err_blocks);
+    return -1;
+}
+
 // Which of the (up to two) problems of a grouped launch this workgroup
 // computes, and its tile origin.
 template <class P>
-__device__ inline bool pick_problem(const P &p0, const P &p1, int tiles_y0, P &out, int &row0,
-                                    int &col0, int block_m = kBlockM)
+__device__ inline bool pick_problem(const P &p0, const P &p1, int tiles_y0, int tiles_x, int tile,
+                                    P &out, int &row0, int &col0, int block_m)
 {
-    const int by = blockIdx.y;
+    const int by = tile / tiles_x;
+    const int bx = tile % tiles_x;
     out = by < tiles_y0 ? p0 : p1;
     if (out.M_dev) {
         const int md = *out.M_dev;
@@ -85,7 +131,7 @@ __device__ inline bool pick_problem(const P &p0, const P &p1, int tiles_y0, P &o
     }
     const int ty = by < tiles_y0 ? by : by - tiles_y0;
     row0 = ty * block_m;
-    col0 = blockIdx.x * kBlockN;
+    col0 = bx * kBlockN;
     return col0 < out.N && row0 < out.M;
 }
 
@@ -153,11 +199,16 @@ constexpr int kF32M = 32 * kF32TM;
 constexpr int kTallRows = 65536;
 
 template <int TM>
-__global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1, int tiles_y0)
+__global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1, int tiles_y0,
+                                                          int tiles_x, int tiles, RmseArgs err,
+                                                          int err_blocks)
 {
+    const int tile = error_blocks(tiles, err, err_blocks);
+    if (tile < 0)
+        return;
     GemmF32 P;
     int brow0, bcol0;
-    if (pick_problem(p0, p1, tiles_y0, P, brow0, bcol0, 32 * TM))
+    if (pick_problem(p0, p1, tiles_y0, tiles_x, tile, P, brow0, bcol0, 32 * TM))
         gemm_f32_tile<TM>(P, brow0, bcol0);
 }
 
@@ -207,12 +258,17 @@ __device__ inline u16x8 load_bf16x8(const uint16_t *ptr, int k, int K)
 }
 
 template <int TM>
-__global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmBF16 p0, GemmBF16 p1, int tiles_y0)
+__global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmBF16 p0, GemmBF16 p1, int tiles_y0,
+                                                           int tiles_x, int tiles, RmseArgs err,
+                                                           int err_blocks)
 {
+    const int tile = error_blocks(tiles, err, err_blocks);
+    if (tile < 0)
+        return;
     constexpr int kTM = TM;
     GemmBF16 P;
     int brow0, bcol0;
-    if (!pick_problem(p0, p1, tiles_y0, P, brow0, bcol0, 32 * TM))
+    if (!pick_problem(p0, p1, tiles_y0, tiles_x, tile, P, brow0, bcol0, 32 * TM))
         return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -276,35 +332,42 @@ __global__ void cast_bf16_kernel(const float *__restrict__ x, uint16_t *__restri
 
 template <class P, class Kern>
 hipError_t launch_grouped(Kern kern, const P &p0, const P *p1, int kid, hipStream_t st,
-                          int block_m = kBlockM)
+                          int block_m, const RmseArgs *err)
 {
     const int ty0 = (p0.M + block_m - 1) / block_m;
     const int ty1 = p1 ? (p1->M + block_m - 1) / block_m : 0;
     int tx = (p0.N + kBlockN - 1) / kBlockN;
     if (p1)
         tx = tx > (p1->N + kBlockN - 1) / kBlockN ? tx : (p1->N + kBlockN - 1) / kBlockN;
+    const int eb = err ? rmse_blocks_dev(err->m) : 0;
+    const long long tiles = (long long)tx * (ty0 + ty1);
+    if (tiles + eb > 0x7fffffffll)
+        return hipErrorInvalidConfiguration;
     prof_begin(kid, st);
-    hipLaunchKernelGGL(kern, dim3(tx, ty0 + ty1), dim3(256), 0, st, p0, p1 ? *p1 : p0, ty0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles + eb)), dim3(256), 0, st, p0, p1 ? *p1 : p0,
+                       ty0, tx, (int)tiles, err ? *err : RmseArgs{}, eb);
     prof_end(kid, st);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st)
+hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st,
+                              const RmseArgs *err)
 {
     const int rows = p0.M > (p1 ? p1->M : 0) ? p0.M : p1->M;
     if (rows >= kTallRows)
-        return launch_grouped(gemm_nt_f32_kernel<4>, p0, p1, kid, st, 128);
-    return launch_grouped(gemm_nt_f32_kernel<kF32TM>, p0, p1, kid, st, kF32M);
+        return launch_grouped(gemm_nt_f32_kernel<4>, p0, p1, kid, st, 128, err);
+    return launch_grouped(gemm_nt_f32_kernel<kF32TM>, p0, p1, kid, st, kF32M, err);
 }
 
-hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st)
+hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st,
+                               const RmseArgs *err)
 {
     const int rows = p0.M > (p1 ? p1->M : 0) ? p0.M : p1->M;
     if (rows >= kTallRows)
-        return launch_grouped(gemm_nt_bf16_kernel<4>, p0, p1, kid, st, 128);
-    return launch_grouped(gemm_nt_bf16_kernel<2>, p0, p1, kid, st, 64);
+        return launch_grouped(gemm_nt_bf16_kernel<4>, p0, p1, kid, st, 128, err);
+    return launch_grouped(gemm_nt_bf16_kernel<2>, p0, p1, kid, st, 64, err);
 }
 
 int gemm_pair_items(const GemmPair &pp) { return gemm_tiles(pp.g) + gemm_tiles(pp.c); }

@@ -1,0 +1,148 @@
+// Device bodies of the error ||Y - D X||_F^2 (FP64 reduction), shared by the
+// error launches and by the launches that carry the error of the previous
+// iteration alongside their own work (the products and the CSR scan).
+#pragma once
+#include "dl_internal.h"
+
+namespace dlk {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Lanes per user row: a power of two >= p/4, each lane owning a float4.
+__device__ inline int lanes_per_user(int p)
+{
+    int l = 1;
+    while (4 * l < p)
+        l <<= 1;
+    return l;
+}
+
+// Partials: one workgroup per block of kRmseSignals signals;
+// the block's X rows are staged in LDS, each lane group forms residual rows 4
+// coordinates per lane with its atom rows loaded four at a time (branch-free,
+// so the loads are in flight together), squares are summed in FP64 and the
+// block's sum is stored.  Final: one workgroup sums the block partials in
+// block order.  The launch boundary orders the two, so no workgroup needs a
+// device-scope fence (which writes the L2 back on a multi-XCD GPU).
+// Workgroups of the partials launch: one per kRmseSignals signals, at most
+// kRmseMaxBlocks (each then strides over several signal blocks), so the final
+// one-workgroup sum stays short.
+constexpr int kRmseMaxBlocks = 1024;
+__host__ __device__ inline int rmse_blocks_dev(int m)
+{
+    const int b = (m + kRmseSignals - 1) / kRmseSignals;
+    return b < kRmseMaxBlocks ? b : kRmseMaxBlocks;
+}
+
+__device__ inline double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum of v over the workgroup (256 threads), in a fixed order; every thread
+// gets the result.
+__device__ inline double block_sum_f64(double v, double *red4)
+{
+    v = wave_sum_f64(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        red4[wave] = v;
+    __syncthreads();
+    return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
+__device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
+{
+    __shared__ double red4[4];
+    __shared__ int sIdx[kRmseSignals * 16];
+    __shared__ float sVal[kRmseSignals * 16];
+    const int p = a.p, s = a.s, n = a.n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lpu = lanes_per_user(p);
+    const int upw = 64 / lpu;
+    const int sub = lane / lpu;
+    const int q = 4 * (lane % lpu);
+    double acc = 0.0;
+    const int nsb = (a.m + kRmseSignals - 1) / kRmseSignals;
+    for (int sb = blk; sb < nsb; sb += nblk) {
+        const int i0 = sb * kRmseSignals;
+        const int nsig = min(kRmseSignals, a.m - i0);
+        __syncthreads();  // the previous signal block's rows are no longer read
+        for (int r = threadIdx.x; r < nsig * s; r += blockDim.x) {
+            int j = a.idx[(size_t)i0 * s + r];
+            float x = a.val[(size_t)i0 * s + r];
+            if (j < 0 || j >= n) {
+                j = 0;  // unused slot: row 0 with a zero coefficient
+                x = 0.f;
+            }
+            sIdx[r] = j;
+            sVal[r] = x;
+        }
+        __syncthreads();
+        // a lane group's signals il0, il0 + G, il0 + 2G, ... (G groups in the
+        // block) are formed together, so all their loads are in flight at once
+        constexpr int RU = 4;
+        const int G = 4 * upw;
+        if (q < p) {
+            for (int il0 = wave * upw + sub; il0 < nsig; il0 += G * RU) {
+                f32x4 e[RU];
+    #pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const int il = il0 + u * G;
+                    e[u] = il < nsig ? *reinterpret_cast<const f32x4 *>(a.Y + (size_t)(i0 + il) * p + q)
+                                     : f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+                for (int t0 = 0; t0 < s; t0 += 4) {
+                    f32x4 d[RU][4];
+                    float x[RU][4];
+    #pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        const int il = il0 + u * G < nsig ? il0 + u * G : il0;
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int t = t0 + v < s ? t0 + v : t0;
+                            x[u][v] = (t0 + v < s && il0 + u * G < nsig) ? sVal[il * s + t] : 0.f;
+                            d[u][v] = *reinterpret_cast<const f32x4 *>(a.D + (size_t)sIdx[il * s + t] * p + q);
+                        }
+                    }
+    #pragma unroll
+                    for (int u = 0; u < RU; ++u)
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            e[u] -= d[u][v] * x[u][v];
+                }
+    #pragma unroll
+                for (int u = 0; u < RU; ++u)
+    #pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc += (double)e[u][r] * (double)e[u][r];
+            }
+        }
+    }
+    const double tot_blk = block_sum_f64(acc, red4);
+    if (threadIdx.x == 0)
+        a.partial[blk] = tot_blk;
+}
+
+// Sum of the nblk block partials in block order, and the error.
+__device__ inline void rmse_final_body(const RmseArgs &a, int nblk)
+{
+    __shared__ double red4[4];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        v += a.partial[b];
+    const double tot = block_sum_f64(v, red4);
+    if (threadIdx.x == 0) {
+        a.out[0] = sqrt(tot / ((double)a.p * (double)a.m));
+        if (!isfinite(tot))
+            atomicAdd(&a.ctl->nonfinite, 1ull);
+    }
+}
+
+}  // namespace
+}  // namespace dlk
