@@ -394,18 +394,26 @@ dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void
     const NormArgs *norm = reinterpret_cast<const NormArgs *>(base + L.norm);
 
     DL_TRY(launch_batched_normalize(norm, list(P.l_quad, count), P.n_quad, st));
+    // As in the single-problem iteration, the error of iteration k is carried
+    // by iteration k+1's launches (partials with the products, final sums
+    // with the CSR scans); the last one runs on its own.  Same bodies and
+    // block decompositions, so every problem gets the same bits either way.
     for (int k = 0; k < iters; ++k) {
         const size_t par = (size_t)(k & 1) * c;
-        DL_TRY(launch_batched_gemm(gemm + par, list(P.l_gemm, count), P.n_gemm, st));
+        const RmseArgs *prev = k > 0 ? rmse + (size_t)((k - 1) & 1) * c : nullptr;
+        DL_TRY(launch_batched_gemm(gemm + par, list(P.l_gemm, count), P.n_gemm, st, prev,
+                                   list(P.l_rmse, count), P.n_rmse));
         for (const Plan::Shape &S : P.shapes)
             DL_TRY(launch_batched_omp(omp + par + S.first, list(S.list, S.num), S.items, S.sh.lps,
                                       S.sh.npl, S.sh.smax, st));
         DL_TRY(launch_batched_csr(csr, list(P.l_count, count), P.n_count, list(P.l_quad, count),
-                                  P.n_quad, list(P.l_scatter, count), P.n_scatter, P.max_n, st));
+                                  P.n_quad, list(P.l_scatter, count), P.n_scatter, P.max_n, st,
+                                  prev, list(P.l_one, count), k - 1));
         DL_TRY(launch_batched_update(upd + par, list(P.l_chunk, count), P.n_chunk, st));
-        DL_TRY(launch_batched_rmse(rmse + par, list(P.l_rmse, count), P.n_rmse,
-                                   list(P.l_one, count), k, st));
     }
+    if (iters > 0)
+        DL_TRY(launch_batched_rmse(rmse + (size_t)((iters - 1) & 1) * c, list(P.l_rmse, count),
+                                   P.n_rmse, list(P.l_one, count), iters - 1, st));
     if (iters % 2 == 1)
         for (int b = 0; b < count; ++b) {
             const dl_params &pq = probs[b].prm;

@@ -281,15 +281,26 @@ __global__ __launch_bounds__(kCsrBlock) void csr_count_batched(const CsrArgs *__
         batch_leave(bl.q, gridDim.x);
 }
 
+// Items past the scans, when etab is set, are the final sums of another
+// iteration's errors (list el, one item per problem), stored to out[k].
 __global__ __launch_bounds__(256) void csr_scan_batched(const CsrArgs *__restrict__ tab,
-                                                        BatchList bl)
+                                                        BatchList bl,
+                                                        const RmseArgs *__restrict__ etab,
+                                                        BatchList el, int k)
 {
     __shared__ int slot;
-    const int total = bl.start[bl.count];
+    const int scans = bl.start[bl.count];
+    const int total = scans + (etab ? el.start[el.count] : 0);
     for (;;) {
         const int it = batch_next_item(bl.q, &slot);
         if (it >= total)
             break;
+        if (it >= scans) {
+            RmseArgs a = etab[batch_find(el.start, el.count, it - scans)];
+            a.out += k;
+            rmse_final_body(a, rmse_blocks_dev(a.m));
+            continue;
+        }
         const int b = batch_find(bl.start, bl.count, it);
         const CsrArgs a = tab[b];
         csr_scan_body(a.blkcnt, a.tot, a.n, csr_nb(a.m), it - bl.start[b]);
@@ -325,7 +336,7 @@ int csr_blocks(int m) { return (m + kCsrBlock - 1) / kCsrBlock; }
 hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, int count_items,
                               const BatchList &scan_list, int scan_items,
                               const BatchList &scatter_list, int scatter_items, int max_n,
-                              hipStream_t st)
+                              hipStream_t st, const RmseArgs *etab, const BatchList &el, int k)
 {
     const size_t shmem = (sizeof(unsigned long long) + sizeof(int32_t)) * kWavesPerBlock * max_n;
     int wg = batch_workers((const void *)csr_count_batched, kCsrBlock, shmem, count_items);
@@ -335,9 +346,11 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    wg = batch_workers((const void *)csr_scan_batched, 256, 0, scan_items);
+    wg = batch_workers((const void *)csr_scan_batched, 256, 0,
+                       scan_items + (etab ? el.count : 0));
     prof_begin(DL_K_CSR_SCAN, st);
-    hipLaunchKernelGGL(csr_scan_batched, dim3(wg), dim3(256), 0, st, tab, scan_list);
+    hipLaunchKernelGGL(csr_scan_batched, dim3(wg), dim3(256), 0, st, tab, scan_list, etab, el,
+                       k);
     prof_end(DL_K_CSR_SCAN, st);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;

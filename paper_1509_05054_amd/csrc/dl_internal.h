@@ -284,14 +284,18 @@ struct GemmPair {
 };
 int batch_workers(const void *kernel, int block, size_t lds, int items);
 int gemm_pair_items(const GemmPair &pp);
+// etab/el/eitems: optional error partials of another iteration (the blocks
+// of each problem's partial pass), run as extra items of the same launch.
 hipError_t launch_batched_gemm(const GemmPair *tab, const BatchList &bl, int items,
-                               hipStream_t st);
+                               hipStream_t st, const RmseArgs *etab = nullptr,
+                               const BatchList &el = BatchList{}, int eitems = 0);
 hipError_t launch_batched_omp(const OmpArgs *tab, const BatchList &bl, int items, int lps,
                               int npl, int smax, hipStream_t st);
 hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, int count_items,
                               const BatchList &scan_list, int scan_items,
                               const BatchList &scatter_list, int scatter_items, int max_n,
-                              hipStream_t st);
+                              hipStream_t st, const RmseArgs *etab = nullptr,
+                              const BatchList &el = BatchList{}, int k = 0);
 hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
                                  int chunk_items, hipStream_t st);
 hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items,

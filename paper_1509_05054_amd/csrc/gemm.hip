@@ -218,16 +218,27 @@ __host__ __device__ inline int gemm_tiles(const GemmF32 &P)
 }
 
 // Batched problems: the items of problem b are the tiles of its Gram matrix,
-// then those of its correlations, row-major over the tile grid.
+// then those of its correlations, row-major over the tile grid.  Items past
+// all tiles, when etab is set, are the error partials of another iteration
+// (list el, the blocks of each problem's partial pass).
 __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmPair *__restrict__ tab,
-                                                           BatchList bl)
+                                                           BatchList bl,
+                                                           const RmseArgs *__restrict__ etab,
+                                                           BatchList el)
 {
     __shared__ int slot;
-    const int total = bl.start[bl.count];
+    const int tiles = bl.start[bl.count];
+    const int total = tiles + (etab ? el.start[el.count] : 0);
     for (;;) {
         const int it = batch_next_item(bl.q, &slot);
         if (it >= total)
             break;
+        if (it >= tiles) {
+            const int e = it - tiles;
+            const int b = batch_find(el.start, el.count, e);
+            rmse_body(etab[b], e - el.start[b], el.start[b + 1] - el.start[b]);
+            continue;
+        }
         const int b = batch_find(bl.start, bl.count, it);
         int t = it - bl.start[b];
         const int tg = gemm_tiles(tab[b].g);
@@ -373,11 +384,13 @@ hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, 
 int gemm_pair_items(const GemmPair &pp) { return gemm_tiles(pp.g) + gemm_tiles(pp.c); }
 
 hipError_t launch_batched_gemm(const GemmPair *tab, const BatchList &bl, int items,
-                               hipStream_t st)
+                               hipStream_t st, const RmseArgs *etab, const BatchList &el,
+                               int eitems)
 {
-    const int wg = batch_workers((const void *)gemm_batched_kernel, 256, 0, items);
+    const int wg = batch_workers((const void *)gemm_batched_kernel, 256, 0,
+                                 items + (etab ? eitems : 0));
     prof_begin(DL_K_CORR, st);
-    hipLaunchKernelGGL(gemm_batched_kernel, dim3(wg), dim3(256), 0, st, tab, bl);
+    hipLaunchKernelGGL(gemm_batched_kernel, dim3(wg), dim3(256), 0, st, tab, bl, etab, el);
     prof_end(DL_K_CORR, st);
     return hipGetLastError();
 }
