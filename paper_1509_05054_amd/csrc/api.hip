@@ -34,7 +34,7 @@ Layout layout_for(const dl_params &prm)
     L.atom_tot = take(sizeof(int32_t) * n);
     L.row_ptr = take(sizeof(int32_t) * (n + 1));
     L.chunk_ptr = take(sizeof(int32_t) * (n + 1));
-    L.users = take(sizeof(int32_t) * m * s);
+    L.uent = take(sizeof(int2) * m * s);
     L.atom_state = take(sizeof(int32_t) * n);
     L.partial = take(sizeof(float) * (size_t)max_chunks(prm) * p);
     L.rmse_part = take(sizeof(double) * (size_t)rmse_blocks(prm.m));
@@ -208,8 +208,11 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
 
 // prev_err: optional error whose partials are complete; its final sum is
 // carried by the scan launch.
+// The users are written as positions (users) or as (position, val there)
+// pairs (uent); either may be null.
 dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, int32_t *users,
-                  float *val_pad, const Ws &ws, hipStream_t st, const RmseArgs *prev_err = nullptr)
+                  int2 *uent, const float *val, float *val_pad, const Ws &ws, hipStream_t st,
+                  const RmseArgs *prev_err = nullptr)
 {
     CsrArgs c;
     c.idx = idx;
@@ -220,6 +223,8 @@ dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, in
     c.row_ptr = row_ptr;
     c.chunk_ptr = ws.at<int32_t>(ws.L.chunk_ptr);
     c.users = users;
+    c.uent = uent;
+    c.val = val;
     c.val_pad = val_pad;
     c.n = prm.n;
     c.m = prm.m;
@@ -235,8 +240,8 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
                      hipStream_t st, const RmseArgs *prev_err = nullptr)
 {
     int32_t *row_ptr = ws.at<int32_t>(ws.L.row_ptr);
-    int32_t *users = ws.at<int32_t>(ws.L.users);
-    dl_status rc = run_csr(prm, idx, row_ptr, users, valn, ws, st, prev_err);
+    int2 *uent = ws.at<int2>(ws.L.uent);
+    dl_status rc = run_csr(prm, idx, row_ptr, nullptr, uent, val, valn, ws, st, prev_err);
     if (rc != DL_OK)
         return rc;
     UpdateArgs u;
@@ -249,7 +254,7 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
     u.E = ws.at<float>(ws.L.E);
     u.row_ptr = row_ptr;
     u.chunk_ptr = ws.at<int32_t>(ws.L.chunk_ptr);
-    u.users = users;
+    u.uent = uent;
     u.atom_state = ws.at<int32_t>(ws.L.atom_state);
     u.partial = ws.at<float>(ws.L.partial);
     u.ctl = ws.ctl();
@@ -403,7 +408,8 @@ dl_status dl_csr(const dl_params *prm, const int32_t *X_idx, int32_t *row_ptr, i
     dl_status rc = check_ws(prm, ws, ws_bytes, &w);
     if (rc != DL_OK)
         return rc;
-    return run_csr(*prm, X_idx, row_ptr, users, nullptr, w, (hipStream_t)stream);
+    return run_csr(*prm, X_idx, row_ptr, users, nullptr, nullptr, nullptr, w,
+                   (hipStream_t)stream);
 }
 
 dl_status dl_jau_update(const dl_params *prm, const float *Y, float *D, const int32_t *X_idx,

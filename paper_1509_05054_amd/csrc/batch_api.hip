@@ -202,7 +202,7 @@ void build_plan(const dl_problem *probs, int count, char *base, const BatchLayou
             u.E = f(W.E);
             u.row_ptr = i32(W.row_ptr);
             u.chunk_ptr = i32(W.chunk_ptr);
-            u.users = i32(W.users);
+            u.uent = reinterpret_cast<const int2 *>(wb + W.uent);
             u.atom_state = i32(W.atom_state);
             u.partial = f(W.partial);
             u.ctl = c;
@@ -236,7 +236,9 @@ void build_plan(const dl_problem *probs, int count, char *base, const BatchLayou
         cs.lrank = i32(W.lrank);
         cs.row_ptr = i32(W.row_ptr);
         cs.chunk_ptr = i32(W.chunk_ptr);
-        cs.users = i32(W.users);
+        cs.users = nullptr;
+        cs.uent = reinterpret_cast<int2 *>(wb + W.uent);
+        cs.val = f(W.val_ws);
         cs.val_pad = pb.X_val;
         cs.n = q.n;
         cs.m = q.m;

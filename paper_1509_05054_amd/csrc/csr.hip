@@ -49,16 +49,29 @@ __device__ inline void csr_count_body(const int32_t *__restrict__ idx, int32_t *
 
     unsigned long long *mymask = masks + wave * n;
     int32_t *mycnt = wcnt + wave * n;
-    const int sig0 = b * kCsrBlock + wave * 64;
+    // the wave's 64 signals hold 64 s consecutive slots; this lane's slot c
+    // is slot 64 c + lane of them, loaded once and kept in registers with its
+    // rank among the wave's users of the same atom
+    constexpr int kMaxS = 16;
+    const size_t pos0 = ((size_t)b * kCsrBlock + wave * 64) * s + lane;
+    const size_t ms = (size_t)m * s;
+    int atoms[kMaxS], rk[kMaxS];
+#pragma unroll
+    for (int c = 0; c < kMaxS; ++c) {
+        atoms[c] = -1;
+        rk[c] = 0;
+        if (c < s && pos0 + 64 * c < ms) {
+            const int atom = idx[pos0 + 64 * c];
+            atoms[c] = atom < n ? atom : -1;  // out-of-range indices are unused slots
+        }
+    }
     const unsigned long long bit = 1ull << lane;
     const unsigned long long lower = bit - 1ull;
-    for (int c = 0; c < s; ++c) {
-        const int e = 64 * c + lane;  // entry inside this wave's 64 x s block
-        const int i = sig0 + e / s;
-        const int t = e % s;
-        int atom = i < m ? idx[(size_t)i * s + t] : -1;
-        if (atom >= n)
-            atom = -1;  // out-of-range indices are treated as unused slots
+#pragma unroll
+    for (int c = 0; c < kMaxS; ++c) {
+        if (c >= s)
+            break;
+        const int atom = atoms[c];
         if (atom >= 0)
             atomicOr(&mymask[atom], bit);
         wave_lds_sync();
@@ -67,7 +80,7 @@ __device__ inline void csr_count_body(const int32_t *__restrict__ idx, int32_t *
         if (atom >= 0) {
             mm = mymask[atom];
             base = mycnt[atom];
-            lrank[(size_t)i * s + t] = base + __popcll(mm & lower);
+            rk[c] = base + __popcll(mm & lower);
         }
         wave_lds_sync();
         if (atom >= 0 && lane == 63 - __clzll((long long)mm)) {
@@ -88,16 +101,10 @@ __device__ inline void csr_count_body(const int32_t *__restrict__ idx, int32_t *
         blkcnt[(size_t)a * nb + b] = run;
     }
     __syncthreads();
-    for (int c = 0; c < s; ++c) {
-        const int e = 64 * c + lane;
-        const int i = sig0 + e / s;
-        const int t = e % s;
-        if (i < m) {
-            const int atom = idx[(size_t)i * s + t];
-            if (atom >= 0 && atom < n)
-                lrank[(size_t)i * s + t] += mycnt[atom];
-        }
-    }
+#pragma unroll
+    for (int c = 0; c < kMaxS; ++c)
+        if (c < s && atoms[c] >= 0)
+            lrank[pos0 + 64 * c] = rk[c] + mycnt[atoms[c]];
 }
 
 __global__ __launch_bounds__(kCsrBlock) void csr_count_kernel(const int32_t *__restrict__ idx,
@@ -230,8 +237,10 @@ __device__ inline void csr_scatter_body(const int32_t *__restrict__ idx,
                                         int32_t *__restrict__ row_ptr,
                                         int32_t *__restrict__ chunk_ptr,
                                         const int32_t *__restrict__ lrank,
-                                        int32_t *__restrict__ users, float *__restrict__ val_pad,
-                                        int n, int m, int s, int nb, int blk, int nblk)
+                                        int32_t *__restrict__ users, int2 *__restrict__ uent,
+                                        const float *__restrict__ val,
+                                        float *__restrict__ val_pad, int n, int m, int s, int nb,
+                                        int blk, int nblk)
 {
     __shared__ int32_t sRow[1025];
     csr_prefix_block(tot, n, sRow, row_ptr, blk == 0 ? chunk_ptr : nullptr);
@@ -245,7 +254,11 @@ __device__ inline void csr_scatter_body(const int32_t *__restrict__ idx,
             continue;
         }
         const int b = (int)(pos / s) / kCsrBlock;
-        users[sRow[atom] + blkoff[(size_t)atom * nb + b] + lrank[pos]] = (int32_t)pos;
+        const int u = sRow[atom] + blkoff[(size_t)atom * nb + b] + lrank[pos];
+        if (users)
+            users[u] = (int32_t)pos;
+        if (uent)
+            uent[u] = make_int2((int)pos, __float_as_int(val[pos]));
     }
 }
 
@@ -253,9 +266,11 @@ __global__ __launch_bounds__(256) void csr_scatter_kernel(
     const int32_t *__restrict__ idx, const int32_t *__restrict__ blkoff,
     const int32_t *__restrict__ tot, int32_t *__restrict__ row_ptr,
     int32_t *__restrict__ chunk_ptr, const int32_t *__restrict__ lrank,
-    int32_t *__restrict__ users, float *__restrict__ val_pad, int n, int m, int s, int nb)
+    int32_t *__restrict__ users, int2 *__restrict__ uent, const float *__restrict__ val,
+    float *__restrict__ val_pad, int n, int m, int s, int nb)
 {
-    csr_scatter_body(idx, blkoff, tot, row_ptr, chunk_ptr, lrank, users, val_pad, n, m, s, nb,
+    csr_scatter_body(idx, blkoff, tot, row_ptr, chunk_ptr, lrank, users, uent, val, val_pad, n,
+                     m, s, nb,
                      blockIdx.x, gridDim.x);
 }
 
@@ -321,7 +336,7 @@ __global__ __launch_bounds__(256) void csr_scatter_batched(const CsrArgs *__rest
         const int b = batch_find(bl.start, bl.count, it);
         const CsrArgs a = tab[b];
         csr_scatter_body(a.idx, a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.lrank, a.users,
-                         a.val_pad, a.n, a.m, a.s, csr_nb(a.m), it - bl.start[b],
+                         a.uent, a.val, a.val_pad, a.n, a.m, a.s, csr_nb(a.m), it - bl.start[b],
                          bl.start[b + 1] - bl.start[b]);
     }
     if (threadIdx.x == 0)
@@ -386,8 +401,8 @@ hipError_t launch_csr(const CsrArgs &a, hipStream_t st, const RmseArgs *err)
         blocks = 8192;
     prof_begin(DL_K_CSR_SCATTER, st);
     hipLaunchKernelGGL(csr_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a.idx,
-                       a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.lrank, a.users, a.val_pad, a.n,
-                       a.m, a.s, nb);
+                       a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.lrank, a.users, a.uent, a.val,
+                       a.val_pad, a.n, a.m, a.s, nb);
     prof_end(DL_K_CSR_SCATTER, st);
     return hipGetLastError();
 }

@@ -42,7 +42,7 @@ struct Layout {
     size_t atom_tot;   // [n] int, users per atom
     size_t row_ptr;    // [n+1] int
     size_t chunk_ptr;  // [n+1] int
-    size_t users;      // [m*s] int
+    size_t uent;       // [m*s] int2: (ELL position, coefficient bits) of every user, in user order
     size_t atom_state; // [n] int: 0 updated, 1 no users, 2 zero F x^T
     size_t partial;    // [max_chunks][p] float
     size_t rmse_part;  // [rmse_blocks(m)] double
@@ -118,7 +118,9 @@ struct CsrArgs {
     int32_t *lrank;      // [m*s]
     int32_t *row_ptr;    // [n+1]
     int32_t *chunk_ptr;  // [n+1]
-    int32_t *users;      // [m*s]
+    int32_t *users;      // optional: ELL positions of the users [m*s]
+    int2 *uent;          // optional: (position, coefficient bits) of the users [m*s]
+    const float *val;    // coefficients [m][s] (with uent)
     float *val_pad;      // optional: zero written at padding slots
     int n, m, s;
 };
@@ -134,7 +136,8 @@ struct UpdateArgs {
     const float *val;     // [m][s] coefficients at the start of the sweep
     float *valn;          // [m][s] refreshed coefficients
     float *E;             // [m][p] residual with the current D, X (kept up to date across groups)
-    const int32_t *row_ptr, *chunk_ptr, *users;
+    const int32_t *row_ptr, *chunk_ptr;
+    const int2 *uent;     // [m*s] (ELL position, val there) of every user, in user order
     int32_t *atom_state;
     float *partial;
     Control *ctl;

@@ -69,20 +69,32 @@ __device__ inline void pass1_body(const UpdateArgs &a, int a0, int a1, int blk, 
         const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
         const int cnt = min(kChunk, a.row_ptr[j + 1] - u0);
         for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
-            const int pos = a.users[u0 + r];
-            sPos[r] = pos;
-            sX[r] = a.val[pos];
+            const int2 ue = a.uent[u0 + r];
+            sPos[r] = ue.x;
+            sX[r] = __int_as_float(ue.y);
         }
         __syncthreads();
         const f32x4 d = load4(a.D + (size_t)j * p, q, p);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         const int stride = 4 * upw;
-#pragma unroll 8
-        for (int r = wave * upw + sub; r < cnt; r += stride) {
-            const int pos = sPos[r];
-            const float x = sX[r];
-            const f32x4 e = load4(a.E + (size_t)(pos / s) * p, q, p);
-            acc += (e + d * x) * x;
+        // the residual rows of U users per lane are loaded before any is
+        // used (in flight together); they are summed in user order
+        constexpr int U = 8;
+        for (int rb = wave * upw + sub; rb < cnt; rb += stride * U) {
+            f32x4 e[U];
+            float x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = rb + u * stride;
+                const bool on = r < cnt;
+                x[u] = on ? sX[r] : 0.f;
+                e[u] = on ? load4(a.E + (size_t)(sPos[r] / s) * p, q, p)
+                          : f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (rb + u * stride < cnt)
+                    acc += (e[u] + d * x[u]) * x[u];
         }
         // sum over the user slots of the wave (lanes with the same q)
         for (int off = lpu; off < 64; off <<= 1) {
@@ -169,9 +181,9 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
         }
         const bool keep = a.rule != DL_RULE_AKSVD || state != 0;
         for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
-            const int pos = a.users[u0 + r];
-            sPos[r] = pos;
-            sX[r] = a.val[pos];
+            const int2 ue = a.uent[u0 + r];
+            sPos[r] = ue.x;
+            sX[r] = __int_as_float(ue.y);
         }
         __syncthreads();
         if (keep) {
@@ -250,7 +262,7 @@ __global__ __launch_bounds__(256) void eupdate_kernel(UpdateArgs a, int a0, int 
         const int u = base + sub;
         if (u >= e1)
             continue;
-        const int pos = a.users[u];
+        const int pos = a.uent[u].x;
         const int i = pos / s;
         const int t0 = pos - i * s;
         const int32_t *row = a.idx + (size_t)i * s;
