@@ -71,11 +71,14 @@ typedef struct dl_params {
     float tol_corr;               /* OMP stops when max |d_j^T r| <= tol_corr * ||y|| (1e-5) */
     float tol_pivot;              /* OMP stops when the FP64 pivot <= tol_pivot * G_jj (1e-10) */
     /* Launch shape of the OMP kernel (0 = default).  A signal is coded by
-       omp_lanes_per_signal lanes (4, 8, 16, 32 or 64) each holding
-       omp_atoms_per_lane correlations (16, or 8 with 8+ lanes); their product
-       must be >= n.  Only the launch shape changes: every value is computed
-       with the same operations, except the summation order of ||y|| in the
-       stop test. */
+       omp_lanes_per_signal lanes (4, 8, 16, 32 or 64, or 128 = two waves
+       with 4 or 8 correlations per lane) each holding omp_atoms_per_lane
+       correlations (4, 8 or 16); their product must be >= n and the lanes
+       at least the sparsity bound (s rounded up to 4, 6, 8, 12 or 16).
+       Only the launch shape changes: every value is computed with the same
+       operations, except the summation order of ||y|| in the stop test
+       (which 128 lanes share with 64).  Batched calls run a 128-lane shape
+       as 64 lanes with twice the correlations per lane. */
     int omp_lanes_per_signal;
     int omp_atoms_per_lane;
 } dl_params;

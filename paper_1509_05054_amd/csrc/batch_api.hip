@@ -88,6 +88,10 @@ OmpShape shape_of(const dl_params &q)
     sh.lps = q.omp_lanes_per_signal > 0 ? q.omp_lanes_per_signal
                                         : omp_lanes_per_signal(q.n, sh.npl, q.s);
     sh.smax = omp_smax(q.s);
+    if (sh.lps == 128) {  // the batched OMP runs one wave per signal: the same values
+        sh.lps = 64;
+        sh.npl *= 2;
+    }
     return sh;
 }
 

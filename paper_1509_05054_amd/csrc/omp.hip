@@ -34,16 +34,21 @@ int omp_lanes_per_signal(int n, int npl, int s)
     return lps;
 }
 
+// 128 lanes per signal: two waves (with 4 or 8 correlations per lane).
 bool omp_config_ok(int n, int s, int lps, int npl)
 {
-    const bool lps_ok = lps == 4 || lps == 8 || lps == 16 || lps == 32 || lps == 64;
+    const bool lps_ok = lps == 4 || lps == 8 || lps == 16 || lps == 32 || lps == 64 ||
+                        (lps == 128 && npl <= 8);
     const bool npl_ok = npl == 4 || npl == 8 || npl == 16;
     return lps_ok && npl_ok && lps * npl >= n && lps >= smax_for(s);
 }
 
-// 16 correlations per lane, fewer when the group must be wide for L anyway.
+// 16 correlations per lane, fewer when the group must be wide for L anyway;
+// more than 512 atoms with s > 8: two waves per signal of 8 per lane.
 int omp_default_npl(int n, int s)
 {
+    if (n > 512 && smax_for(s) >= 12)
+        return 8;  // omp_lanes_per_signal then gives 128
     int npl = 16;
     while (npl > 4 && omp_lanes_per_signal(n, npl, s) * (npl / 2) >= n &&
            omp_lanes_per_signal(n, npl / 2, s) == omp_lanes_per_signal(n, npl, s))

@@ -155,10 +155,20 @@ __device__ inline void load_row(vec_t<NPL> &v, const float *row, int first, int 
 
 // The GPW = 64 / LPS signals [wave_sig0, wave_sig0 + GPW) of one wave
 // (signals at or beyond m_eff are skipped); waves never wait for each other.
-template <int LPS, int NPL, int SMAX>
+//
+// WPS = 2 (with LPS = 64): one signal per two-wave workgroup.  Wave w holds
+// the correlations of atoms [64 NPL w, 64 NPL (w + 1)); both waves keep their
+// own copy of L and the coefficients and take every step with the same
+// operations on the same values, so they make the same decisions and their
+// correlations match those of one 128-lane group exactly.  The only exchange
+// is the step's argmax, through LDS with one workgroup barrier (two slots by
+// step parity, so a slot is rewritten only after both waves have read it).
+// Wave 0 writes the outputs and the counters.
+template <int LPS, int NPL, int SMAX, int WPS = 1>
 __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int m_eff)
 {
     static_assert(LPS >= SMAX, "one lane per row of L");
+    static_assert(WPS == 1 || (WPS == 2 && LPS == 64), "two waves per signal need LPS = 64");
     constexpr int GPW = 64 / LPS;                 // signals per wave
     constexpr int US = SMAX > 1 ? SMAX - 1 : 1;   // stored u vectors
     // rare FP64 pivot path only
@@ -166,9 +176,13 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
     __shared__ float sB[kWaves][GPW][SMAX];
     __shared__ double sW[kWaves][GPW][SMAX];
     __shared__ double sD2[kWaves][GPW];
+    __shared__ float sPairV[2][2];  // [step parity][wave]: the waves' argmax
+    __shared__ int sPairI[2][2];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const int wsub = WPS == 2 ? (wave & 1) : 0;  // this wave's half of the atoms
+    const bool lead = wsub == 0;                 // writes outputs and counters
     const int grp = lane / LPS;   // signal slot of this lane in the wave
     const int l = lane % LPS;     // lane within the group
     const int i = wave_sig0 + grp;
@@ -186,7 +200,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
     const float thr = a.tol_corr * ynorm;
 
     // correlations of y; atoms beyond n are marked as taken
-    const int a_first = l * NPL;
+    const int a_first = (wsub * LPS + l) * NPL;
     vec_t<NPL> alpha;
     load_row<NPL>(alpha, a.A0 + (size_t)i * ldn, a_first, ldn, valid);
     unsigned taken = 0;
@@ -210,7 +224,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         js[t] = 0;
     }
     bool active = valid && isfinite(ynorm);
-    if (valid && !isfinite(ynorm) && l == 0)
+    if (lead && valid && !isfinite(ynorm) && l == 0)
         atomicAdd(&a.ctl->nonfinite, 1ull);
     int kg = 0;  // atoms selected for this lane's signal
 
@@ -231,6 +245,17 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
             bidx = b ? a_first + c : bidx;
         }
         group_argmax<LPS>(best, bidx);
+        if constexpr (WPS == 2) {
+            if (l == 0) {
+                sPairV[k & 1][wsub] = best;
+                sPairI[k & 1][wsub] = bidx;
+            }
+            __syncthreads();
+            // both waves combine the two in the same order
+            best = sPairV[k & 1][0];
+            bidx = sPairI[k & 1][0];
+            take_better(best, bidx, sPairV[k & 1][1], sPairI[k & 1][1]);
+        }
         bool ok = active && best > thr && bidx < n;
         const int j = ok ? bidx : 0;
         const float *Gj = a.G + (size_t)j * ldn;
@@ -290,7 +315,8 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
                     d2_64 -= sW[wave][grp][t] * sW[wave][grp][t];
                 }
                 sD2[wave][grp] = d2_64;
-                atomicAdd(&a.ctl->fp64_pivot_recomputes, 1ull);
+                if (lead)
+                    atomicAdd(&a.ctl->fp64_pivot_recomputes, 1ull);
             }
             wave_lds_sync();
             if (need64) {
@@ -335,7 +361,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
                     u[t] = unew;
         }
         if (ok) {
-            if (l == j / NPL)
+            if (wsub * LPS + l == j / NPL)  // the lane holding atom j
                 taken |= 1u << (j % NPL);
 #pragma unroll
             for (int t = 0; t < SMAX; ++t)
@@ -360,7 +386,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         }
         return true;
     });
-    if (valid && l == 0 && kg < s)
+    if (lead && valid && l == 0 && kg < s)
         atomicAdd(&a.ctl->early_stops, 1ull);
 
     // coefficients: L^T x = c, from the last row up; lane t holds L[t][*]
@@ -376,6 +402,8 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
             xown = xs[r];
     }
     // output row of this signal
+    if (!lead)
+        return;
     const int io = (valid && a.rowmap) ? a.rowmap[i] : i;
     if (valid && l < s) {
         const bool on = l < kg;
@@ -421,6 +449,20 @@ void omp_kernel(OmpArgs a)
     if (wave_sig0 >= m_eff)
         return;  // whole wave leaves together; no workgroup barrier follows
     omp_signals<LPS, NPL, SMAX>(a, wave_sig0, m_eff);
+}
+
+// One signal per two-wave workgroup (WPS = 2 above).  At n = 1024, s = 12 a
+// wave of the one-wave shape needs 11 u-vectors of 16 values per lane (256
+// VGPRs + AGPRs: one wave per SIMD); split over two waves it fits two per
+// SIMD without spills (measured: 1.58 -> 1.33 ms per coding pass at m =
+// 65536; forcing three per SIMD spills and was slower).
+template <int NPL, int SMAX>
+__global__ __launch_bounds__(128) void omp_pair_kernel(OmpArgs a)
+{
+    const int m_eff = a.m_dev ? min(*a.m_dev, a.m) : a.m;
+    if ((int)blockIdx.x >= m_eff)
+        return;  // both waves leave together
+    omp_signals<64, NPL, SMAX, 2>(a, (int)blockIdx.x, m_eff);
 }
 
 // Batched problems of one launch shape: every wave takes items (GPW signals
@@ -469,6 +511,26 @@ hipError_t launch_omp_t(const OmpArgs &a, hipStream_t st)
     hipLaunchKernelGGL((omp_kernel<LPS, NPL, SMAX>), dim3(blocks), dim3(64 * kWaves), 0, st, a);
     prof_end(DL_K_OMP, st);
     return hipGetLastError();
+}
+
+template <int NPL, int SMAX>
+hipError_t launch_omp_pair_t(const OmpArgs &a, hipStream_t st)
+{
+    prof_begin(DL_K_OMP, st);
+    hipLaunchKernelGGL((omp_pair_kernel<NPL, SMAX>), dim3(a.m), dim3(128), 0, st, a);
+    prof_end(DL_K_OMP, st);
+    return hipGetLastError();
+}
+
+// Two waves per signal (lanes_per_signal = 128), for sparsity bounds above 6.
+template <int NPL>
+hipError_t launch_omp_pair_s(const OmpArgs &a, hipStream_t st)
+{
+    if (a.s <= 8)
+        return launch_omp_pair_t<NPL, 8>(a, st);
+    if (a.s <= 12)
+        return launch_omp_pair_t<NPL, 12>(a, st);
+    return launch_omp_pair_t<NPL, 16>(a, st);
 }
 
 template <int LPS, int NPL>

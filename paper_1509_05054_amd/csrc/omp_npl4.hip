@@ -12,6 +12,7 @@ hipError_t launch_omp_npl4(const OmpArgs &a, int lps, hipStream_t st)
     case 16: return launch_omp_s<16, 4>(a, st);
     case 32: return launch_omp_s<32, 4>(a, st);
     case 64: return launch_omp_s<64, 4>(a, st);
+    case 128: return launch_omp_pair_s<4>(a, st);
     default: return hipErrorInvalidValue;
     }
 }

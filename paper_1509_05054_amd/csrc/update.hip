@@ -136,6 +136,41 @@ __device__ inline float block_sum_f32(float v, float *red4)
     return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
+// x' = (e + d x)^T d' for the chunk's users staged in sPos/sX; every lane of
+// the wave runs the same trip count (shuffles below), and the residual rows
+// of U users per lane are loaded before any of them is used, so their loads
+// are in flight together.
+template <int U>
+__device__ inline void pass2_refresh(const UpdateArgs &a, f32x4 d, f32x4 dn, const int *sPos,
+                                     const float *sX, int cnt, int wave, int lane, int lpu,
+                                     int upw, int sub, int q)
+{
+    const int p = a.p, s = a.s;
+    const int stride = 4 * upw;
+    for (int rb = wave * upw; rb < cnt; rb += stride * U) {
+        f32x4 e[U];
+        float x[U];
+        int pos[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = rb + u * stride + sub;
+            const bool on = r < cnt;
+            pos[u] = on ? sPos[r] : -1;
+            x[u] = on ? sX[r] : 0.f;
+            e[u] = on ? load4(a.E + (size_t)(pos[u] / s) * p, q, p) : f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const f32x4 f = e[u] + d * x[u];
+            float part = f[0] * dn[0] + f[1] * dn[1] + f[2] * dn[2] + f[3] * dn[3];
+            for (int off = 1; off < lpu; off <<= 1)
+                part += __shfl_xor(part, off);
+            if (pos[u] >= 0 && (lane % lpu) == 0)
+                a.valn[pos[u]] = part;
+        }
+    }
+}
+
 __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, int nblk)
 {
     __shared__ int sPos[kChunk];
@@ -193,34 +228,12 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
             const f32x4 d = load4(a.D + (size_t)j * p, q, p);
             const f32x4 dn = q < p ? *reinterpret_cast<const f32x4 *>(sDn + q)
                                    : f32x4{0.f, 0.f, 0.f, 0.f};
-            const int stride = 4 * upw;
-            // every lane of the wave runs the same trip count (shuffles below);
-            // the residual rows of U users per lane are loaded before any of
-            // them is used, so their loads are in flight together
-            constexpr int U = 4;
-            for (int rb = wave * upw; rb < cnt; rb += stride * U) {
-                f32x4 e[U];
-                float x[U];
-                int pos[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int r = rb + u * stride + sub;
-                    const bool on = r < cnt;
-                    pos[u] = on ? sPos[r] : -1;
-                    x[u] = on ? sX[r] : 0.f;
-                    e[u] = on ? load4(a.E + (size_t)(pos[u] / s) * p, q, p)
-                              : f32x4{0.f, 0.f, 0.f, 0.f};
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const f32x4 f = e[u] + d * x[u];
-                    float part = f[0] * dn[0] + f[1] * dn[1] + f[2] * dn[2] + f[3] * dn[3];
-                    for (int off = 1; off < lpu; off <<= 1)
-                        part += __shfl_xor(part, off);
-                    if (pos[u] >= 0 && (lane % lpu) == 0)
-                        a.valn[pos[u]] = part;
-                }
-            }
+            // rows in flight per lane: 8 for short signals, 4 for long ones
+            // (measured: 8 is 5% faster at p = 64 and 20% slower at p = 256)
+            if (lpu <= 16)
+                pass2_refresh<8>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
+            else
+                pass2_refresh<4>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
         }
         __syncthreads();
     }
@@ -472,7 +485,10 @@ unsigned grid_for(size_t items, unsigned cap)
 
 int rmse_blocks(int m) { return rmse_blocks_dev(m); }
 
-bool error_defer_ok(int m) { return (m + kRmseSignals - 1) / kRmseSignals <= kRmseMaxBlocks; }
+// Deferred (carried by the next iteration's launches) up to 1024 signal
+// blocks: measured faster there, and slower at 16384 blocks, where the
+// partial workgroups form a tail behind the product tiles.
+bool error_defer_ok(int m) { return (m + kRmseSignals - 1) / kRmseSignals <= 1024; }
 
 int max_chunks(const dl_params &prm)
 {

@@ -353,7 +353,31 @@ def test_iterate_is_deterministic_and_resumable():
     np.testing.assert_array_equal(np.concatenate([ra, rb]), r1)
 
 
-@pytest.mark.parametrize("lps,npl", [(16, 16), (32, 8), (64, 4), (64, 16), (32, 16)])
+@pytest.mark.parametrize("s,m", [(12, 2001), (16, 777), (8, 513)])
+def test_omp_two_waves_per_signal_bitwise(s, m):
+    """128 lanes per signal (two waves, atoms split between them, argmax
+    exchanged through LDS) against one 64-lane wave holding twice the
+    correlations per lane: every correlation, pivot and coefficient goes
+    through the same operations, so supports, coefficients, residual norms
+    and counters agree bit for bit."""
+    note(f"omp two waves per signal n=1024 s={s} m={m}")
+    Y, D = _patch_problem(256, 1024, m, seed=91 + s)
+    i0, v0, st0 = gpu_omp(D, Y, s, omp_lanes_per_signal=64, omp_atoms_per_lane=16)
+    i1, v1, st1 = gpu_omp(D, Y, s, omp_lanes_per_signal=128, omp_atoms_per_lane=8)
+    np.testing.assert_array_equal(i0, i1)
+    np.testing.assert_array_equal(v0, v1)
+    for key in ("fp64_pivot_recomputes", "early_stops", "nonfinite"):
+        assert st0[key] == st1[key], (key, st0[key], st1[key])
+    # half the atoms per wave: 4 per lane (n = 512 fits 128 x 4)
+    Y2, D2 = _patch_problem(64, 512, 600, seed=17)
+    i2, v2, _ = gpu_omp(D2, Y2, s, omp_lanes_per_signal=64, omp_atoms_per_lane=8)
+    i3, v3, _ = gpu_omp(D2, Y2, s, omp_lanes_per_signal=128, omp_atoms_per_lane=4)
+    np.testing.assert_array_equal(i2, i3)
+    np.testing.assert_array_equal(v2, v3)
+
+
+@pytest.mark.parametrize("lps,npl", [(16, 16), (32, 8), (64, 4), (64, 16), (32, 16), (128, 8),
+                                     (128, 4)])
 def test_omp_launch_shapes_agree(lps, npl):
     """Every launch shape of the OMP kernel computes the same supports and
     coefficients (only the summation order of ||y|| differs)."""
