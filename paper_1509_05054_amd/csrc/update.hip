@@ -485,10 +485,10 @@ unsigned grid_for(size_t items, unsigned cap)
 
 int rmse_blocks(int m) { return rmse_blocks_dev(m); }
 
-// Deferred (carried by the next iteration's launches) up to 1024 signal
-// blocks: measured faster there, and slower at 16384 blocks, where the
-// partial workgroups form a tail behind the product tiles.
-bool error_defer_ok(int m) { return (m + kRmseSignals - 1) / kRmseSignals <= 1024; }
+// Deferred (carried by the next iteration's launches) up to 16384 signals:
+// measured faster there, and slower at 262144, where the partial workgroups
+// each stride over many blocks and form a tail behind the product tiles.
+bool error_defer_ok(int m) { return m <= 16384; }
 
 int max_chunks(const dl_params &prm)
 {
