@@ -288,8 +288,9 @@ __device__ inline void gemm_f32_tile_direct(const GemmF32 &P, int brow0, int bco
 }
 
 // 128-row tiles stage their operands in LDS, 64-row tiles load them
-// directly (measured: staging is 20% faster for the tall products, and 7%
-// slower for 64-row tiles, whose LDS stage costs workgroups per CU).
+// directly (measured: staging is 20% faster for 128-row tiles of the tall
+// products, and 7% slower for 64-row tiles, whose LDS stage costs
+// workgroups per CU).
 template <int TM>
 __device__ inline void gemm_f32_tile_sel(const GemmF32 &P, int brow0, int bcol0)
 {
@@ -299,12 +300,12 @@ __device__ inline void gemm_f32_tile_sel(const GemmF32 &P, int brow0, int bcol0)
         gemm_f32_tile_direct<TM>(P, brow0, bcol0);
 }
 
-// FP32 products use workgroup tiles of 32 TM rows: TM = 2 (64 rows) for the
-// batched and smaller products, TM = 4 (128 rows) once the products have
-// many rows (measured: 64 rows faster at m = 16384, 128 rows at m = 262144).
+// Workgroup tiles of 32 TM rows: single-problem launches use TM = 4 (128
+// rows, LDS-staged operands; measured faster than 64-row tiles at m = 16384
+// as well as at 262144), the items of batched launches TM = 2 (64 rows,
+// direct loads: many small products, where more workgroups per CU pay).
 constexpr int kF32TM = 2;
 constexpr int kF32M = 32 * kF32TM;
-constexpr int kTallRows = 65536;
 
 template <int TM>
 __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1, int tiles_y0,
@@ -510,19 +511,13 @@ hipError_t launch_grouped(Kern kern, const P &p0, const P *p1, int kid, hipStrea
 hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st,
                               const RmseArgs *err)
 {
-    const int rows = p0.M > (p1 ? p1->M : 0) ? p0.M : p1->M;
-    if (rows >= kTallRows)
-        return launch_grouped(gemm_nt_f32_kernel<4>, p0, p1, kid, st, 128, err);
-    return launch_grouped(gemm_nt_f32_kernel<kF32TM>, p0, p1, kid, st, kF32M, err);
+    return launch_grouped(gemm_nt_f32_kernel<4>, p0, p1, kid, st, 128, err);
 }
 
 hipError_t launch_gemm_nt_bf16(const GemmBF16 &p0, const GemmBF16 *p1, int kid, hipStream_t st,
                                const RmseArgs *err)
 {
-    const int rows = p0.M > (p1 ? p1->M : 0) ? p0.M : p1->M;
-    if (rows >= kTallRows)
-        return launch_grouped(gemm_nt_bf16_kernel<4>, p0, p1, kid, st, 128, err);
-    return launch_grouped(gemm_nt_bf16_kernel<2>, p0, p1, kid, st, 64, err);
+    return launch_grouped(gemm_nt_bf16_kernel<4>, p0, p1, kid, st, 128, err);
 }
 
 int gemm_pair_items(const GemmPair &pp) { return gemm_tiles(pp.g) + gemm_tiles(pp.c); }
