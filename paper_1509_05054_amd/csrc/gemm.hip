@@ -2,10 +2,9 @@
 //   G  = D D^T   [n][n]  (Gram matrix of the atoms)
 //   A0 = Y D^T   [m][n]  (correlations D^T y of every signal)
 // Both are "NT" products C[M][N] = A[M][K] B[N][K]^T of row-major operands
-// whose K dimension (the signal size p) is contiguous.  64-row tiles load
-// short contiguous K-slices per lane straight from global memory into the
-// MFMA layout; 128-row tiles (and BF16 products) stage row segments of the
-// operands in LDS first (coalesced loads, see gemm_f32_tile).
+// whose K dimension (the signal size p) is contiguous.  Workgroup tiles of
+// 128 rows stage row segments of the operands in LDS (coalesced loads, see
+// gemm_f32_tile) and feed the MFMAs from there.
 //
 // MFMA layout used (16x16 output tile, wave64): lane l supplies row l%16 of
 // the A-tile and column l%16 of the B-tile over a K-slice chosen by l/16, and
@@ -69,34 +68,6 @@ __device__ inline void store_block(float *C, int M, int N, int ldc, int brow0, i
         }
     }
     __syncthreads();  // sC is reused by the next tile of a persistent workgroup
-}
-
-// Direct stores for products computed with the operands swapped (the MFMA
-// gets B as its first operand): lane l then holds C[l%16][4*(l/16) + r] of
-// each 16x16 tile, four consecutive columns, written as one 16-byte store.
-template <int TM>
-__device__ inline void store_direct(float *C, int M, int N, int ldc, int row0, int col0,
-                                    const f32x4 (&acc)[TM][kTN])
-{
-    const int lane = threadIdx.x & 63;
-    const bool vec_ok = (ldc % 4) == 0 && ((uintptr_t)C % 16) == 0;
-#pragma unroll
-    for (int a = 0; a < TM; ++a) {
-        const int row = row0 + 16 * a + (lane & 15);
-        if (row >= M)
-            continue;
-#pragma unroll
-        for (int b = 0; b < kTN; ++b) {
-            const int col = col0 + 16 * b + 4 * (lane >> 4);
-            float *dst = C + (size_t)row * ldc + col;
-            if (vec_ok && col + 3 < N) {
-                *reinterpret_cast<f32x4 *>(dst) = acc[a][b];
-            } else {
-                for (int q = 0; q < 4 && col + q < N; ++q)
-                    dst[q] = acc[a][b][q];
-            }
-        }
-    }
 }
 
 // The grid is one-dimensional (row tiles may exceed the 65535 limit of the
@@ -231,80 +202,11 @@ __device__ inline void gemm_f32_tile(const GemmF32 &P, int brow0, int bcol0)
     store_block<TM, BM>(P.C, M, N, P.ldc, brow0, bcol0, acc, lds);
 }
 
-// The same tile with each lane loading its MFMA operands straight from
-// global memory into the MFMA layout (no LDS stage).
-template <int TM>
-__device__ inline void gemm_f32_tile_direct(const GemmF32 &P, int brow0, int bcol0)
-{
-    constexpr int kTM = TM;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int row0 = brow0 + (wave >> 1) * 16 * kTM;
-    const int col0 = bcol0 + (wave & 1) * 16 * kTN;
-    const int r = lane & 15;
-    const int kq = 4 * (lane >> 4);  // this lane's K offset inside a 16-wide K step
-    const int M = P.M, N = P.N, K = P.K;
-
-    f32x4 acc[kTM][kTN];
-#pragma unroll
-    for (int a = 0; a < kTM; ++a)
-#pragma unroll
-        for (int b = 0; b < kTN; ++b)
-            acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        f32x4 av[2][kTM], bv[2][kTN];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int k = k0 + 16 * h + kq;
-#pragma unroll
-            for (int a = 0; a < kTM; ++a) {
-                const int row = row0 + 16 * a + r;
-                av[h][a] = f32x4{0.f, 0.f, 0.f, 0.f};
-                if (row < M && k < K)
-                    av[h][a] = *reinterpret_cast<const f32x4 *>(P.A + (size_t)row * K + k);
-            }
-#pragma unroll
-            for (int b = 0; b < kTN; ++b) {
-                const int col = col0 + 16 * b + r;
-                bv[h][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-                if (col < N && k < K)
-                    bv[h][b] = *reinterpret_cast<const f32x4 *>(P.B + (size_t)col * K + k);
-            }
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int a = 0; a < kTM; ++a)
-#pragma unroll
-                    for (int b = 0; b < kTN; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h][a][q], bv[h][b][q],
-                                                                          acc[a][b], 0, 0, 0);
-    }
-    __shared__ float sC[32 * TM * kStageLd];
-    store_block<TM, 32 * TM>(P.C, M, N, P.ldc, brow0, bcol0, acc, sC);
-}
-
-// 128-row tiles stage their operands in LDS, 64-row tiles load them
-// directly (measured: staging is 20% faster for 128-row tiles of the tall
-// products, and 7% slower for 64-row tiles, whose LDS stage costs
-// workgroups per CU).
-template <int TM>
-__device__ inline void gemm_f32_tile_sel(const GemmF32 &P, int brow0, int bcol0)
-{
-    if constexpr (TM == 4)
-        gemm_f32_tile<TM>(P, brow0, bcol0);
-    else
-        gemm_f32_tile_direct<TM>(P, brow0, bcol0);
-}
-
-// Workgroup tiles of 32 TM rows: single-problem launches use TM = 4 (128
-// rows, LDS-staged operands; measured faster than 64-row tiles at m = 16384
-// as well as at 262144), the items of batched launches TM = 2 (64 rows,
-// direct loads: many small products, where more workgroups per CU pay).
-constexpr int kF32TM = 2;
+// Workgroup tiles of 128 rows (TM = 4) for single-problem and batched
+// products alike (measured: faster than 64-row tiles that load their
+// operands straight into the MFMA layout, at m = 16384 and 262144 and for
+// the batched problems).
+constexpr int kF32TM = 4;
 constexpr int kF32M = 32 * kF32TM;
 
 template <int TM>
@@ -318,7 +220,7 @@ __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmF32 p0, GemmF32 p1
     GemmF32 P;
     int brow0, bcol0;
     if (pick_problem(p0, p1, tiles_y0, tiles_x, tile, P, brow0, bcol0, 32 * TM))
-        gemm_f32_tile_sel<TM>(P, brow0, bcol0);
+        gemm_f32_tile<TM>(P, brow0, bcol0);
 }
 
 __host__ __device__ inline int gemm_tiles(const GemmF32 &P)
@@ -355,7 +257,7 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmPair *__res
         if (t >= tg)
             t -= tg;
         const int tx = (P.N + kBlockN - 1) / kBlockN;
-        gemm_f32_tile_sel<kF32TM>(P, (t / tx) * kF32M, (t % tx) * kBlockN);
+        gemm_f32_tile<kF32TM>(P, (t / tx) * kF32M, (t % tx) * kBlockN);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
