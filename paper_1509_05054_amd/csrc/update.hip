@@ -171,6 +171,9 @@ __device__ inline void pass2_refresh(const UpdateArgs &a, f32x4 d, f32x4 dn, con
     }
 }
 
+// U: residual rows in flight per lane in the refresh (a template parameter,
+// so that each choice is a kernel with its own register allocation).
+template <int U>
 __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, int nblk)
 {
     __shared__ int sPos[kChunk];
@@ -228,12 +231,7 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
             const f32x4 d = load4(a.D + (size_t)j * p, q, p);
             const f32x4 dn = q < p ? *reinterpret_cast<const f32x4 *>(sDn + q)
                                    : f32x4{0.f, 0.f, 0.f, 0.f};
-            // rows in flight per lane: 8 for short signals, 4 for long ones
-            // (measured: 8 is 5% faster at p = 64 and 20% slower at p = 256)
-            if (lpu <= 16)
-                pass2_refresh<8>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
-            else
-                pass2_refresh<4>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
+            pass2_refresh<U>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
         }
         __syncthreads();
     }
@@ -251,9 +249,10 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
     }
 }
 
+template <int U>
 __global__ __launch_bounds__(256) void pass2_kernel(UpdateArgs a, int a0, int a1)
 {
-    pass2_body(a, a0, a1, blockIdx.x, gridDim.x);
+    pass2_body<U>(a, a0, a1, blockIdx.x, gridDim.x);
 }
 
 // ---- incremental error update after a group (group sizes below n) -------
@@ -399,7 +398,7 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restri
         if (STAGE == 0)
             pass1_body(a, 0, a.n, t, nt);
         else
-            pass2_body(a, 0, a.n, t, nt);
+            pass2_body<4>(a, 0, a.n, t, nt);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -516,7 +515,12 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
         if (e != hipSuccess)
             return e;
         prof_begin(DL_K_UPD_PASS2, st);
-        hipLaunchKernelGGL(pass2_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
+        // residual rows in flight per lane: 8 for short signals, 4 for long
+        // ones (measured: 8 is 5% faster at p = 64 and 20% slower at p = 256)
+        if (a.p <= 64)
+            hipLaunchKernelGGL(pass2_kernel<8>, dim3(grid), dim3(256), 0, st, a, a0, a1);
+        else
+            hipLaunchKernelGGL(pass2_kernel<4>, dim3(grid), dim3(256), 0, st, a, a0, a1);
         prof_end(DL_K_UPD_PASS2, st);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
