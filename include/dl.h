@@ -325,9 +325,10 @@ dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void
                              size_t ws_bytes, dl_stream_t stream);
 
 /* Autotuner of the OMP launch shape: for every distinct (p, n, s) it times
-   each valid (omp_lanes_per_signal, omp_atoms_per_lane) on the largest such
-   problem (its first 65536 signals, correlations from its current D, `reps`
-   timed launches after one warm-up, 1 <= reps <= 1000) and writes the
+   each valid one-wave (omp_lanes_per_signal, omp_atoms_per_lane) with the
+   OMP kernel of dl_iterate_batched on the largest such problem (its first
+   65536 signals, correlations from its current D, `reps` timed launches
+   after one warm-up, 1 <= reps <= 1000) and writes the
    fastest into prm of every problem with that (p, n, s); the default shape
    is kept unless another is at least 5% faster.  Synchronous;
    overwrites X_idx and X_val of the problems it times, not D.  Workspace as

@@ -498,6 +498,17 @@ dl_status dl_autotune(dl_problem *probs, int count, int reps, void *ws, size_t w
         a.pivot_fp64 = q.pivot_fp64_threshold;
         a.tol_corr = q.tol_corr;
         a.tol_pivot = q.tol_pivot;
+        // candidates are timed with the batched OMP kernel (the one the shape
+        // is for) on a batch of this one problem: its argument table and item
+        // list go to the start of the workspace's OMP table and list regions
+        // (iterate_batched rewrites both)
+        OmpArgs *tab = reinterpret_cast<OmpArgs *>(base + L.omp);
+        int32_t *lst = reinterpret_cast<int32_t *>(base + L.lists);
+        BatchQueue *queue = reinterpret_cast<BatchQueue *>(base + L.queue);
+        if (hipMemcpyAsync(tab, &a, sizeof(OmpArgs), hipMemcpyHostToDevice, st) != hipSuccess) {
+            rc = DL_EHIP;
+            break;
+        }
         float best_ms = -1.f, default_ms = -1.f;
         int best_lps = 0, best_npl = 0;
         dl_params dq = q;
@@ -508,20 +519,28 @@ dl_status dl_autotune(dl_problem *probs, int count, int reps, void *ws, size_t w
             for (int lps : {4, 8, 16, 32, 64}) {
                 if (!omp_config_ok(q.n, q.s, lps, npl) || rc != DL_OK)
                     continue;
-                a.lanes_per_signal = lps;
-                a.atoms_per_lane = npl;
+                const int gpw = omp_signals_per_item(lps);
+                const int items = (a.m + gpw - 1) / gpw;
+                const int32_t start[2] = {0, items};  // alive until the event wait below
+                const BatchList one{lst, 1, queue};
+                const int smax = omp_smax(q.s);
                 float ms = 0.f;
-                if (launch_omp(a, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
+                if (hipMemcpyAsync(lst, start, sizeof(start), hipMemcpyHostToDevice, st) !=
+                        hipSuccess ||
+                    launch_batched_omp(tab, one, items, lps, npl, smax, st) != hipSuccess ||
+                    hipEventRecord(e0, st) != hipSuccess) {
                     rc = DL_EHIP;
+                    hipStreamSynchronize(st);  // the copy reads `start`
                     break;
                 }
                 for (int r = 0; r < reps && rc == DL_OK; ++r)
-                    if (launch_omp(a, st) != hipSuccess)
+                    if (launch_batched_omp(tab, one, items, lps, npl, smax, st) != hipSuccess)
                         rc = DL_EHIP;
                 if (rc != DL_OK || hipEventRecord(e1, st) != hipSuccess ||
                     hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                     rc = DL_EHIP;
+                    hipStreamSynchronize(st);
                     break;
                 }
                 if (lps == def.lps && npl == def.npl)
