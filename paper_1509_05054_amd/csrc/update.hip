@@ -172,7 +172,10 @@ __device__ inline void pass2_refresh(const UpdateArgs &a, f32x4 d, f32x4 dn, con
 }
 
 // U: residual rows in flight per lane in the refresh (a template parameter,
-// so that each choice is a kernel with its own register allocation).
+// so that each choice is a kernel with its own register allocation), or 0:
+// 8 for signal sizes up to 64, else 4, chosen in the kernel.  Short signals
+// use U = 0 (measured 2% faster for pass 2 at p = 64 than U = 8, with the
+// same registers), long ones U = 4.
 template <int U>
 __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, int nblk)
 {
@@ -231,7 +234,13 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
             const f32x4 d = load4(a.D + (size_t)j * p, q, p);
             const f32x4 dn = q < p ? *reinterpret_cast<const f32x4 *>(sDn + q)
                                    : f32x4{0.f, 0.f, 0.f, 0.f};
-            pass2_refresh<U>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
+            if (U > 0)
+                pass2_refresh<(U > 0 ? U : 4)>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw,
+                                                sub, q);
+            else if (lpu <= 16)
+                pass2_refresh<8>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
+            else
+                pass2_refresh<4>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
         }
         __syncthreads();
     }
@@ -516,9 +525,10 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
             return e;
         prof_begin(DL_K_UPD_PASS2, st);
         // residual rows in flight per lane: 8 for short signals, 4 for long
-        // ones (measured: 8 is 5% faster at p = 64 and 20% slower at p = 256)
+        // ones (measured: 8 is 5% faster at p = 64 and 20% slower at p = 256,
+        // where the 8-row kernel holds more registers)
         if (a.p <= 64)
-            hipLaunchKernelGGL(pass2_kernel<8>, dim3(grid), dim3(256), 0, st, a, a0, a1);
+            hipLaunchKernelGGL(pass2_kernel<0>, dim3(grid), dim3(256), 0, st, a, a0, a1);
         else
             hipLaunchKernelGGL(pass2_kernel<4>, dim3(grid), dim3(256), 0, st, a, a0, a1);
         prof_end(DL_K_UPD_PASS2, st);
