@@ -129,8 +129,8 @@ dl_status products(const dl_params &prm, const float *D, const float *Y, float *
                    const Ws *ws, hipStream_t st, int ldn, const int32_t *m_dev = nullptr,
                    const RmseArgs *prev_err = nullptr)
 {
-    if (prev_err && !(G && A0))
-        return DL_EINVAL;
+    if (prev_err && (!(G && A0) || !prev_err->Dold))
+        return DL_EINVAL;  // the launch carries only the refreshing error pass
     if (prm.precision == DL_PREC_BF16) {
         uint16_t *Dbf = ws->at<uint16_t>(ws->L.Dbf);
         uint16_t *Ybf = ws->at<uint16_t>(ws->L.Ybf);
@@ -235,9 +235,12 @@ dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, in
 
 // One atom-update sweep reading (D, val) and writing (Dn, valn); E must hold
 // Y - D X on entry.
+// error_refreshes: the error pass that follows forms valn (all atoms in one
+// group only); pass 2 then only forms Dn and the atom states.
 dl_status run_update(const dl_params &prm, const float *Y, const float *D, float *Dn,
                      const int32_t *idx, const float *val, float *valn, const Ws &ws,
-                     hipStream_t st, const RmseArgs *prev_err = nullptr)
+                     hipStream_t st, const RmseArgs *prev_err = nullptr,
+                     bool error_refreshes = false)
 {
     int32_t *row_ptr = ws.at<int32_t>(ws.L.row_ptr);
     int2 *uent = ws.at<int2>(ws.L.uent);
@@ -265,6 +268,7 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
     u.group_size = prm.group_size;
     u.rule = prm.rule;
     u.max_chunks = max_chunks(prm);
+    u.no_refresh = error_refreshes ? 1 : 0;
     DL_TRY(launch_update(u, st));
     return DL_OK;
 }
@@ -480,7 +484,13 @@ static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, in
     // launches, so the same bits.  Larger counts (each partial workgroup
     // striding over several blocks) keep the error launches, which measured
     // faster there.  The last iteration's deferred error runs on its own.
-    const bool defer = error_defer_ok(q.m);
+    // With all atoms in one group the refreshed X is read only by the error
+    // and returned: the error pass forms it (pass 2 only forms d'), reading
+    // the residual E, the coefficients and the dictionary the coding used,
+    // none of which is overwritten before iteration k+1's coding.  The
+    // carried error needs that refresh, so it is used at group size n only.
+    const bool one_group = q.group_size >= q.n;
+    const bool defer = one_group && error_defer_ok(q.m);
     RmseArgs prev{};
     bool pending = false;
     for (int k = 0; k < iters; ++k) {
@@ -492,10 +502,19 @@ static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, in
             return rc;
         if (hist)
             DL_TRY(launch_copy(X_idx, hist + (size_t)k * ms, 4 * ms, st));
-        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st, pending ? &prev : nullptr);
+        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st, pending ? &prev : nullptr,
+                        one_group);
         if (rc != DL_OK)
             return rc;
         prev = rmse_args(q, Y, Dnext, X_idx, X_val, rmse + k, w);
+        if (one_group) {
+            prev.Dold = Dcur;
+            prev.E = w.at<float>(w.L.E);
+            prev.val_old = val_ws;
+            prev.atom_state = w.at<int32_t>(w.L.atom_state);
+            prev.valn = X_val;
+            prev.rule = q.rule;
+        }
         pending = defer;
         if (!defer)
             DL_TRY(launch_rmse(prev, st));

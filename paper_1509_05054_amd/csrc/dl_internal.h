@@ -146,6 +146,7 @@ struct UpdateArgs {
     float *partial;
     Control *ctl;
     int p, n, m, s, group_size, rule, max_chunks;
+    int no_refresh;  // 1: pass 2 only forms d' (the error pass refreshes X)
 };
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
 
@@ -157,6 +158,16 @@ struct RmseArgs {
     double *out;      // one double
     Control *ctl;
     int p, n, m, s;
+    // Optional refresh (all atoms in one group): with Dold set, the pass also
+    // forms the refreshed coefficients val = (e + d x)^T d' (eq. 5, second
+    // line) from the coefficients val_old, residual E and dictionary Dold
+    // before the update (D is the updated one), writes them to valn, and
+    // measures the error with them.  Atoms whose atom_state is not 0, and the
+    // SGK rule, keep their coefficients.
+    const float *Dold = nullptr, *E = nullptr, *val_old = nullptr;
+    const int32_t *atom_state = nullptr;
+    float *valn = nullptr;
+    int rule = 0;
 };
 hipError_t launch_rmse(const RmseArgs &a, hipStream_t st);
 // Whether an error over m signals is one signal block per partial workgroup

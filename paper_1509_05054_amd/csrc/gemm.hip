@@ -74,7 +74,8 @@ __device__ inline void store_block(float *C, int M, int N, int ldc, int brow0, i
 // y dimension): workgroup t < tiles computes tile (t % tiles_x, t / tiles_x)
 // of the grid of output tiles, row-major as a two-dimensional launch would
 // order them.  The err_blocks workgroups after the tiles carry the partial
-// pass of an error (measured: faster behind the tiles than ahead of them).
+// pass of an error with the coefficient refresh (measured: faster behind the
+// tiles than ahead of them).
 // Returns the tile index, or -1 for the error workgroups after running their
 // share.
 __device__ inline int error_blocks(int tiles, const RmseArgs &err, int err_blocks)
@@ -83,7 +84,7 @@ __device__ inline int error_blocks(int tiles, const RmseArgs &err, int err_block
     if (w < tiles)
         return w;
     if (w - tiles < err_blocks)
-        rmse_body(err, w - tiles, err_blocks);
+        rmse_refresh_body(err, w - tiles, err_blocks);
     return -1;
 }
 

@@ -26,12 +26,6 @@ namespace dlk {
 namespace {
 
 
-__device__ inline f32x4 load4(const float *base, int q, int p)
-{
-    if (q < p)
-        return *reinterpret_cast<const f32x4 *>(base + q);
-    return f32x4{0.f, 0.f, 0.f, 0.f};
-}
 
 // Atom of global chunk gc among atoms [a0, a1): chunk_ptr[j] <= gc < chunk_ptr[j+1].
 __device__ inline int chunk_atom(const int32_t *chunk_ptr, int a0, int a1, int gc)
@@ -196,6 +190,8 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
         const int gc = cbase + c;
         const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
         const int c0 = a.chunk_ptr[j], c1 = a.chunk_ptr[j + 1];
+        if (a.no_refresh && gc != c0)
+            continue;  // only the atom's first chunk forms d' (uniform branch)
         const int u0 = a.row_ptr[j] + (gc - c0) * kChunk;
         const int cnt = min(kChunk, a.row_ptr[j + 1] - u0);
         // g_j = sum of the atom's chunk partials, in chunk order
@@ -220,6 +216,8 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
                     atomicAdd(&a.ctl->nonfinite, 1ull);
             }
         }
+        if (a.no_refresh)
+            continue;  // the error pass refreshes X
         const bool keep = a.rule != DL_RULE_AKSVD || state != 0;
         for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
             const int2 ue = a.uent[u0 + r];
@@ -310,9 +308,13 @@ __global__ __launch_bounds__(256) void eupdate_kernel(UpdateArgs a, int a0, int 
     }
 }
 
+template <bool REFRESH>
 __global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
 {
-    rmse_body(a, blockIdx.x, gridDim.x);
+    if constexpr (REFRESH)
+        rmse_refresh_body(a, blockIdx.x, gridDim.x);
+    else
+        rmse_body(a, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void rmse_final_kernel(RmseArgs a, int nblk)
@@ -594,7 +596,10 @@ hipError_t launch_rmse(const RmseArgs &a, hipStream_t st)
 {
     const int nb = rmse_blocks(a.m);
     prof_begin(DL_K_RMSE, st);
-    hipLaunchKernelGGL(rmse_kernel, dim3(nb), dim3(256), 0, st, a);
+    if (a.Dold)
+        hipLaunchKernelGGL(rmse_kernel<true>, dim3(nb), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(rmse_kernel<false>, dim3(nb), dim3(256), 0, st, a);
     prof_end(DL_K_RMSE, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
