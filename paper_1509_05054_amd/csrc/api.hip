@@ -291,6 +291,20 @@ RmseArgs rmse_args(const dl_params &prm, const float *Y, const float *D, const i
     return r;
 }
 
+// The error pass also forms the refreshed coefficients valn from the
+// coefficients val_old, the residual E and the dictionary Dold the coding
+// used (all atoms in one group, after an update with error_refreshes).
+void add_refresh(RmseArgs &r, const dl_params &prm, const float *Dold, const float *val_old,
+                 float *valn, const Ws &ws)
+{
+    r.Dold = Dold;
+    r.E = ws.at<float>(ws.L.E);
+    r.val_old = val_old;
+    r.atom_state = ws.at<int32_t>(ws.L.atom_state);
+    r.valn = valn;
+    r.rule = prm.rule;
+}
+
 dl_status run_rmse(const dl_params &prm, const float *Y, const float *D, const int32_t *idx,
                    const float *val, double *out, const Ws &ws, hipStream_t st)
 {
@@ -507,14 +521,8 @@ static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, in
         if (rc != DL_OK)
             return rc;
         prev = rmse_args(q, Y, Dnext, X_idx, X_val, rmse + k, w);
-        if (one_group) {
-            prev.Dold = Dcur;
-            prev.E = w.at<float>(w.L.E);
-            prev.val_old = val_ws;
-            prev.atom_state = w.at<int32_t>(w.L.atom_state);
-            prev.valn = X_val;
-            prev.rule = q.rule;
-        }
+        if (one_group)
+            add_refresh(prev, q, Dcur, val_ws, X_val, w);
         pending = defer;
         if (!defer)
             DL_TRY(launch_rmse(prev, st));
@@ -660,12 +668,15 @@ dl_status dl_iterate_proposed(const dl_params *prm, const dl_proposal *pr, const
             if (rc != DL_OK)
                 return rc;
         }
-        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st);
+        // all atoms in one group: the error pass refreshes X (as in iterate_impl)
+        const bool one_group = q.group_size >= q.n;
+        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st, nullptr, one_group);
         if (rc != DL_OK)
             return rc;
-        rc = run_rmse(q, Y, Dnext, X_idx, X_val, rmse + k, w, st);
-        if (rc != DL_OK)
-            return rc;
+        RmseArgs ra = rmse_args(q, Y, Dnext, X_idx, X_val, rmse + k, w);
+        if (one_group)
+            add_refresh(ra, q, Dcur, val_ws, X_val, w);
+        DL_TRY(launch_rmse(ra, st));
         float *t = Dcur;
         Dcur = Dnext;
         Dnext = t;
