@@ -339,6 +339,36 @@ def test_iterate_free_running_full_size(gs):
     assert abs(gpu_rmse(w.Y, Dg, ig, vg) - rg[-1]) / rg[-1] < 1e-6
 
 
+@pytest.mark.parametrize("m,rule", [(3000, dl.RULE_AKSVD), (20000, dl.RULE_AKSVD),
+                                    (3000, dl.RULE_SGK)])
+def test_iterate_refresh_in_error_pass_bitwise(m, rule):
+    """With all atoms in one group the iteration forms the refreshed X in the
+    error pass (carried into the next products launch up to 16384 signals,
+    on its own above; the SGK rule keeps X).  One iteration equals the
+    explicit coding, update (refresh in pass 2) and error calls bit for bit:
+    the same D, X and error."""
+    w = synth.workload("patches_p64_n256_s6_m16384", m=m)
+    note(f"iterate refresh in error pass m={m} rule={rule}")
+    prm = dl.Params(w.p, w.n, w.m, w.s, group_size=w.n, rule=rule)
+    ws = dl.workspace(prm)
+    Yg = dev(w.Y)
+    idx = torch.empty((w.m, w.s), dtype=torch.int32, device="cuda")
+    val = torch.empty((w.m, w.s), dtype=torch.float32, device="cuda")
+    r = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    D1 = dev(w.D0)
+    dl.iterate(prm, Yg, D1, 1, idx, val, r, ws)
+    Dn = dev(w.D0)
+    dl.iterate(prm, Yg, Dn, 0, idx, val, r[:0], ws)  # the normalised D0 the coding used
+    D0n = host(Dn)
+    i2, v2, _ = gpu_omp(D0n, w.Y, w.s)
+    D2, x2, _ = gpu_update(w.Y, D0n, i2, v2, w.n, rule)
+    r2 = gpu_rmse(w.Y, D2.astype(np.float32), i2, x2.astype(np.float32))
+    np.testing.assert_array_equal(host(idx), i2)
+    np.testing.assert_array_equal(host(val), x2.astype(np.float32))
+    np.testing.assert_array_equal(host(D1), D2.astype(np.float32))
+    assert float(host(r)[0]) == r2, (float(host(r)[0]), r2)
+
+
 def test_iterate_is_deterministic_and_resumable():
     w = synth.workload("patches_p64_n256_s6_m16384", m=6000)
     note("iterate determinism / resume")
