@@ -72,6 +72,8 @@ def _load():
         lib.dlo_iterate.restype = None
         lib.dlo_max_threads.argtypes = []
         lib.dlo_max_threads.restype = c_int
+        lib.dlo_set_threads.argtypes = [c_int]
+        lib.dlo_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -147,6 +149,11 @@ def jau_update(Y, D, idx, val, group_size, rule=RULE_AKSVD, atoms=None):
 def max_threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(_load().dlo_max_threads())
+
+
+def set_threads(threads: int) -> None:
+    """Number of OpenMP threads of the oracle's later calls (timing only)."""
+    _load().dlo_set_threads(int(threads))
 
 
 def normalize(D):

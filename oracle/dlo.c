@@ -336,3 +336,6 @@ void dlo_iterate(int p, int n, int m, int s, const double *Y, double *D, int ite
 
 /* Threads the oracle's parallel loops use. */
 int dlo_max_threads(void) { return omp_get_max_threads(); }
+
+/* Set the number of threads of the following parallel loops (for timing). */
+void dlo_set_threads(int threads) { omp_set_num_threads(threads > 0 ? threads : 1); }

@@ -101,6 +101,38 @@ def test_adam_step_and_loss_decrease():
     assert losses[-1] < 0.9 * losses[0] and all(b < a for a, b in zip(losses, losses[1:])), losses
 
 
+def test_adam_steps_match_oracle_element_by_element():
+    """Four consecutive Adam steps on one fixed batch: each step's gradients
+    (computed on the GPU at the current weights) are fed to the oracle's Adam,
+    whose FP64 moments and bias corrections (1 - b^t for t = 1..4) must give
+    the GPU's FP32 master weights after every step."""
+    note("mlp adam steps 1..4 against the oracle")
+    B = 256
+    q, vec, ws = _net(batch=B, seed=6)
+    w, idx = _data(1024)
+    pairs = dev(np.random.default_rng(8).permutation(w.m)[:B].astype(np.int32), torch.int32)
+    Yd, hd = dev(w.Y), dev(idx, torch.int32)
+    params = synth.unpack_mlp(vec.astype(np.float64), SIZES)
+    state = learned.adam_init(params)
+    gbuf = torch.empty(vec.size, device="cuda")
+    pbuf = torch.empty(vec.size, device="cuda")
+    for t in range(1, 5):
+        dl.mlp_train_step(q, ws, Yd, hd, pairs, step=t)
+        dl.mlp_read(q, ws, params=pbuf, grads=gbuf)
+        g = synth.unpack_mlp(host(gbuf).astype(np.float64), SIZES)
+        # the hyperparameters as the library holds them (FP32)
+        f = lambda v: float(np.float32(v))  # noqa: E731
+        params, state = learned.adam_step(params, g, state, t=t, lr=f(q.lr), b1=f(q.beta1),
+                                          b2=f(q.beta2), eps=f(q.eps))
+        want = np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params])
+        got = host(pbuf).astype(np.float64)
+        err = np.abs(got - want)
+        # FP32 master weights and moments: a few ulps of the weights plus the
+        # FP32 rounding of b2^t (relative 1.5e-5 of 1 - b2^t at t = 2), which
+        # moves a step of lr = 3e-3 by about 5e-8
+        assert np.all(err <= 1e-5 * np.abs(want) + 3e-7), (t, float(err.max()))
+
+
 @pytest.mark.parametrize("cols,k", [(256, 12), (1024, 24), (40, 5)])
 def test_topk_exact(cols, k):
     note(f"topk cols={cols} k={k}")

@@ -68,6 +68,42 @@ def test_adam_first_step_is_signed_learning_rate():
         np.testing.assert_allclose(b - bn, 1e-3 * gb / (np.abs(gb) + 1e-8), rtol=1e-12)
 
 
+def test_adam_constant_gradient_moves_by_signed_learning_rate_every_step():
+    """With the same gradient g at every step the moments are m_t = (1 - b1^t) g
+    and v_t = (1 - b2^t) g^2, so the bias-corrected moments are g and g^2 at
+    every t and each step moves by lr * g / (|g| + eps).  Dividing by
+    (1 - b) instead of (1 - b^t) breaks this from the second step on."""
+    rng = np.random.default_rng(7)
+    params = _small_params(rng)
+    grads = [(rng.standard_normal(W.shape), rng.standard_normal(b.shape)) for W, b in params]
+    state = learned.adam_init(params)
+    cur = params
+    steps = 5
+    for t in range(1, steps + 1):
+        cur, state = learned.adam_step(cur, grads, state, t=t, lr=2e-3)
+    for (W, b), (Wn, bn), (gW, gb) in zip(params, cur, grads):
+        np.testing.assert_allclose(W - Wn, steps * 2e-3 * gW / (np.abs(gW) + 1e-8), rtol=1e-9)
+        np.testing.assert_allclose(b - bn, steps * 2e-3 * gb / (np.abs(gb) + 1e-8), rtol=1e-9)
+
+
+def test_adam_two_steps_hand_computed():
+    """Scalar weight 1, gradients 1 then -2, lr 0.1, b1 0.9, b2 0.999, eps 0.
+    By hand: step 1 gives m = 0.1, v = 0.001, corrected 1 and 1, so w = 0.9.
+    Step 2: m = 0.09 - 0.2 = -0.11 and v = 0.000999 + 0.004 = 0.004999;
+    corrected by 1 - 0.81 = 0.19 and 1 - 0.998001 = 0.001999 they are -11/19
+    and 4999/1999, so w = 0.9 + 0.1 (11/19) / sqrt(4999/1999) = 0.93661035..."""
+    p0 = [(np.array([[1.0]]), np.array([0.0]))]
+    g1 = [(np.array([[1.0]]), np.array([0.0]))]
+    g2 = [(np.array([[-2.0]]), np.array([0.0]))]
+    st = learned.adam_init(p0)
+    p1, st = learned.adam_step(p0, g1, st, t=1, lr=0.1, eps=0.0)
+    assert abs(p1[0][0][0, 0] - 0.9) < 1e-15
+    p2, st = learned.adam_step(p1, g2, st, t=2, lr=0.1, eps=0.0)
+    assert abs(p2[0][0][0, 0] - 0.9366103527035843) < 1e-13
+    mW, vW, _, _ = st[0]
+    assert abs(mW[0, 0] + 0.11) < 1e-15 and abs(vW[0, 0] - 0.004999) < 1e-15
+
+
 def test_removal_cost_equals_explicit_refit():
     """Dropping atom j from a least-squares fit raises ||r||^2 by exactly
     c_j^2 / [(D_C^T D_C)^{-1}]_jj."""
