@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 RULE_AKSVD = 0
 RULE_SGK = 1
+RULE_NSGK = 2
 
 # Stop thresholds shared with the GPU path's documented reading of the
 # paper's silent points (see the module docstring of dlo.c).
@@ -65,6 +66,9 @@ def _load():
         lib.dlo_jau_update_range.argtypes = [c_int, c_int, c_int, c_int, dp, dp, ip, dp, c_int,
                                              c_int, c_int, c_int]
         lib.dlo_jau_update_range.restype = c_long
+        lib.dlo_nsgk_update_range.argtypes = [c_int, c_int, c_int, c_int, dp, dp, ip, dp, ip,
+                                              dp, c_int, c_int, c_int]
+        lib.dlo_nsgk_update_range.restype = c_long
         lib.dlo_normalize.argtypes = [c_int, c_int, dp]
         lib.dlo_normalize.restype = None
         lib.dlo_iterate.argtypes = [c_int, c_int, c_int, c_int, dp, dp, c_int, c_int, c_int,
@@ -144,6 +148,24 @@ def jau_update(Y, D, idx, val, group_size, rule=RULE_AKSVD, atoms=None):
     unused = lib.dlo_jau_update_range(p, n, m, s, _dp(Y), _dp(D), _ip(idx), _dp(val),
                                       int(group_size), int(rule), int(a0), int(a1))
     return D, val, int(unused)
+
+
+def nsgk_update(Y, D, idx, val, idx_prev, val_prev, group_size, atoms=None):
+    """P-NSGK atom update (eq. 7 with the P-SGK group loop) of ``D`` = D^(k),
+    given this iteration's representations X^(k) (``idx``/``val``) and the
+    previous ones X^(k-1) (``idx_prev``/``val_prev``); returns
+    ``(D_new, unused_atoms)``.  The representations are not changed."""
+    lib = _load()
+    Y, idx, idx_prev = _f64(Y), _i32(idx), _i32(idx_prev)
+    val, val_prev = _f64(val), _f64(val_prev)
+    D = _f64(D).copy()
+    n, p = D.shape
+    m, s = idx.shape
+    a0, a1 = (0, n) if atoms is None else atoms
+    unused = lib.dlo_nsgk_update_range(p, n, m, s, _dp(Y), _dp(D), _ip(idx), _dp(val),
+                                       _ip(idx_prev), _dp(val_prev), int(group_size), int(a0),
+                                       int(a1))
+    return D, int(unused)
 
 
 def max_threads() -> int:

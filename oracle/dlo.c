@@ -23,6 +23,9 @@
  *   - An atom with no users, or whose F x^T is zero, keeps its value.
  *   - Group g covers atoms [g*gs, min((g+1)*gs, n)); groups run in index order.
  *   - The error is measured after the atom update, with the refreshed X.
+ *   - P-NSGK: the group error is E = Z - D X^(k-1) with Z of eq. (7), the users
+ *     I_j are those of X^(k-1); the first iteration, which has no earlier
+ *     representation, takes X^(k-1) = X^(k) (then Z = Y and it is P-SGK).
  */
 #include <math.h>
 #include <omp.h>
@@ -32,6 +35,7 @@
 
 #define DLO_RULE_AKSVD 0
 #define DLO_RULE_SGK 1
+#define DLO_RULE_NSGK 2
 
 static double dot(const double *a, const double *b, int p)
 {
@@ -298,6 +302,85 @@ long dlo_jau_update_range(int p, int n, int m, int s, const double *Y, double *D
     return unused;
 }
 
+/*
+ * Atom-update stage of P-NSGK (Sec. 3): the P-SGK group loop applied to the
+ * modified signals of eq. (7),
+ *     Z = Y + D^(k) X^(k-1) - D^(k) X^(k),
+ * with the representations X^(k-1) that the iteration started from in place
+ * of X^(k) (ELL idx_prev/val_prev; X^(k) is idx/val).  D holds D^(k) on entry.
+ * For every group the error is E = Z - D X^(k-1) with the current D (step 2
+ * of Alg. 2 with Y replaced by Z and X by X^(k-1)), every atom of the group
+ * reads the same group-start D and E (eq. 2), I_j are the signals whose
+ * X^(k-1) uses d_j, F = E_{I_j} + d_j x_{j,I_j} (eq. 3) and
+ * d_j = F x^T / (x x^T) (eq. 6), then normalised.  Neither X is changed.
+ * Only atoms [first_atom, end_atom) are visited.  Returns the number of atom
+ * updates skipped because the atom had no users in X^(k-1).
+ */
+long dlo_nsgk_update_range(int p, int n, int m, int s, const double *Y, double *D,
+                           const int32_t *idx, const double *val, const int32_t *idx_prev,
+                           const double *val_prev, int group_size, int first_atom,
+                           int end_atom)
+{
+    double *Dk = (double *)malloc(sizeof(double) * (size_t)n * p);
+    double *Z = (double *)malloc(sizeof(double) * (size_t)m * p);
+    double *E = (double *)malloc(sizeof(double) * (size_t)m * p);
+    double *Dn = (double *)malloc(sizeof(double) * (size_t)n * p);
+    long unused = 0;
+    memcpy(Dk, D, sizeof(double) * (size_t)n * p);
+    memcpy(Dn, D, sizeof(double) * (size_t)n * p);
+
+    /* Z = (Y - D^(k) X^(k)) + D^(k) X^(k-1) */
+    dlo_residual(p, m, s, Y, Dk, idx, val, Z);
+    for (int i = 0; i < m; ++i)
+        for (int t = 0; t < s; ++t) {
+            int j = idx_prev[(size_t)i * s + t];
+            if (j < 0)
+                continue;
+            double x = val_prev[(size_t)i * s + t];
+            for (int q = 0; q < p; ++q)
+                Z[(size_t)i * p + q] += Dk[(size_t)j * p + q] * x;
+        }
+
+    for (int a0 = first_atom; a0 < end_atom; a0 += group_size) {
+        int a1 = a0 + group_size < end_atom ? a0 + group_size : end_atom;
+        dlo_residual(p, m, s, Z, D, idx_prev, val_prev, E);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : unused)
+        for (int j = a0; j < a1; ++j) {
+            const double *dj = D + (size_t)j * p;
+            double *g = (double *)calloc((size_t)p, sizeof(double));
+            double xx = 0.0;
+            long users = 0;
+            for (size_t e = 0; e < (size_t)m * s; ++e) {
+                if (idx_prev[e] != j)
+                    continue;
+                size_t i = e / (size_t)s;
+                double x = val_prev[e];
+                for (int q = 0; q < p; ++q)
+                    g[q] += (E[i * p + q] + dj[q] * x) * x;
+                xx += x * x;
+                ++users;
+            }
+            if (users == 0) {
+                ++unused;
+            } else if (sqrt(dot(g, g, p)) > 0.0) {
+                double *dn = Dn + (size_t)j * p;
+                for (int q = 0; q < p; ++q)
+                    dn[q] = g[q] / xx;
+                double dnn = sqrt(dot(dn, dn, p));
+                for (int q = 0; q < p; ++q)
+                    dn[q] /= dnn;
+            }
+            free(g);
+        }
+        memcpy(D + (size_t)a0 * p, Dn + (size_t)a0 * p, sizeof(double) * (size_t)(a1 - a0) * p);
+    }
+    free(Dk);
+    free(Z);
+    free(E);
+    free(Dn);
+    return unused;
+}
+
 long dlo_jau_update(int p, int n, int m, int s, const double *Y, double *D,
                     const int32_t *idx, double *val, int group_size, int rule)
 {
@@ -326,12 +409,33 @@ void dlo_iterate(int p, int n, int m, int s, const double *Y, double *D, int ite
                  int group_size, int rule, double tol_corr, double tol_pivot,
                  int32_t *idx, double *val, double *rmse)
 {
+    /* P-NSGK keeps the representations the iteration started from; the first
+       iteration has none before it and starts from its own X^(0) (so Z = Y). */
+    int32_t *idx_prev = NULL;
+    double *val_prev = NULL;
+    if (rule == DLO_RULE_NSGK) {
+        idx_prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * s);
+        val_prev = (double *)malloc(sizeof(double) * (size_t)m * s);
+    }
     dlo_normalize(p, n, D);
     for (int k = 0; k < iters; ++k) {
         dlo_omp(p, n, m, s, D, Y, tol_corr, tol_pivot, idx, val);
-        dlo_jau_update(p, n, m, s, Y, D, idx, val, group_size, rule);
+        if (rule == DLO_RULE_NSGK) {
+            if (k == 0) {
+                memcpy(idx_prev, idx, sizeof(int32_t) * (size_t)m * s);
+                memcpy(val_prev, val, sizeof(double) * (size_t)m * s);
+            }
+            dlo_nsgk_update_range(p, n, m, s, Y, D, idx, val, idx_prev, val_prev, group_size,
+                                  0, n);
+            memcpy(idx_prev, idx, sizeof(int32_t) * (size_t)m * s);
+            memcpy(val_prev, val, sizeof(double) * (size_t)m * s);
+        } else {
+            dlo_jau_update(p, n, m, s, Y, D, idx, val, group_size, rule);
+        }
         rmse[k] = dlo_rmse(p, m, s, Y, D, idx, val);
     }
+    free(idx_prev);
+    free(val_prev);
 }
 
 /* Threads the oracle's parallel loops use. */
