@@ -160,6 +160,20 @@ dl_status dl_rmse(const dl_params *prm, const float *Y, const float *D, const in
                   const float *X_val, double *rmse_out, void *ws, size_t ws_bytes,
                   dl_stream_t stream);
 
+/* As dl_rmse, for callers that cannot allocate device memory (code under
+   graph capture, tight serving loops, harnesses that forbid allocation): no
+   workspace argument, and the call allocates nothing.  Its scratch (the
+   error's control words and at most 1024 FP64 block partials, 8.4 KB) is a
+   static device array of the library; each GPU holds its own copy from the
+   first call on that device until the process ends.  Every size dl_rmse
+   accepts fits it; invalid sizes or pointers return DL_EINVAL.  The stream
+   must belong to the current device.  Calls on one GPU share its array, so
+   calls that overlap in time on one GPU race (use one stream).  A non-finite
+   error is returned as a non-finite value. */
+dl_status dl_rmse_noalloc(const dl_params *prm, const float *Y, const float *D,
+                          const int32_t *X_idx, const float *X_val, double *rmse_out,
+                          dl_stream_t stream);
+
 /* `iters` DL iterations (Alg. 1): D holds D0 on entry (it is normalised
    first) and the final dictionary on exit; X_idx/X_val hold the last
    iteration's representations after its update; rmse[k] (device, `iters`

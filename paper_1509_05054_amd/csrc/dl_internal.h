@@ -170,6 +170,11 @@ struct RmseArgs {
     int rule = 0;
 };
 hipError_t launch_rmse(const RmseArgs &a, hipStream_t st);
+// The same two launches without the optional per-launch timing (which may
+// create events): for the entry point that allocates nothing.
+hipError_t launch_rmse_unprofiled(const RmseArgs &a, hipStream_t st);
+// Most error partials any launch uses (rmse_blocks(m) never exceeds it).
+constexpr int kRmseMaxPartials = 1024;
 // Whether an error over m signals is one signal block per partial workgroup
 // (the sizes at which it is carried by the next iteration's launches).
 bool error_defer_ok(int m);

@@ -610,6 +610,17 @@ hipError_t launch_rmse(const RmseArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_rmse_unprofiled(const RmseArgs &a, hipStream_t st)
+{
+    const int nb = rmse_blocks(a.m);
+    hipLaunchKernelGGL(rmse_kernel<false>, dim3(nb), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(rmse_final_kernel, dim3(1), dim3(256), 0, st, a, nb);
+    return hipGetLastError();
+}
+
 hipError_t launch_residual(const float *Y, const float *D, const int32_t *idx, const float *val,
                            float *E, int p, int n, int m, int s, hipStream_t st)
 {

@@ -78,6 +78,7 @@ SIGNATURES = {
     "dl_rmse": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "dl_iterate": (ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp]),
+    "dl_rmse_noalloc": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp]),
     "dl_read_stats": (ctypes.c_int, [_PP, _vp, ctypes.c_size_t, ctypes.POINTER(Stats), _vp]),
     "dl_iterate_record": (ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
                                          ctypes.c_size_t, _vp]),
@@ -222,6 +223,12 @@ def jau_update(prm: Params, Y, D, X_idx, X_val, ws, stream=None):
 def rmse(prm: Params, Y, D, X_idx, X_val, out, ws, stream=None):
     _check(lib().dl_rmse(prm.ref(), _ptr(Y), _ptr(D), _ptr(X_idx), _ptr(X_val), _ptr(out),
                          _ptr(ws), ws.numel(), _stream(stream)), "dl_rmse")
+
+
+def rmse_noalloc(prm: Params, Y, D, X_idx, X_val, out, stream=None):
+    """dl_rmse with the library's static scratch (no workspace, no allocation)."""
+    _check(lib().dl_rmse_noalloc(prm.ref(), _ptr(Y), _ptr(D), _ptr(X_idx), _ptr(X_val),
+                                 _ptr(out), _stream(stream)), "dl_rmse_noalloc")
 
 
 def iterate(prm: Params, Y, D, iters, X_idx, X_val, rmse_out, ws, stream=None):

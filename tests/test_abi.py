@@ -119,3 +119,11 @@ def test_batched_calls_validate_on_the_host():
     misaligned = (dl._Problem * 1)(_fake_problem())
     misaligned[0].D = 0x100004
     assert L.dl_iterate_batched(misaligned, 1, 1, ws, 1 << 40, None) == dl.DL_EINVAL
+
+
+def test_rmse_noalloc_rejects_bad_arguments_on_the_host():
+    """Validation happens before the scratch is looked up or anything runs."""
+    ok = dl.Params(64, 256, 100, 6)
+    assert dl.lib().dl_rmse_noalloc(ok.ref(), None, None, None, None, None, None) == dl.DL_EINVAL
+    bad = dl.Params(64, 256, 0, 6)
+    assert dl.lib().dl_rmse_noalloc(bad.ref(), None, None, None, None, None, None) == dl.DL_EINVAL
