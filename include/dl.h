@@ -59,8 +59,14 @@ typedef enum {
 typedef enum { DL_PREC_FP32 = 0, DL_PREC_BF16 = 1 } dl_precision;
 
 /* Atom rule.  AK-SVD (eq. 5): d = F x^T / ||F x^T||, then x = F^T d (X is
-   refreshed).  SGK (eq. 6): d = F x^T / (x x^T), normalised; X unchanged. */
-typedef enum { DL_RULE_AKSVD = 0, DL_RULE_SGK = 1 } dl_rule;
+   refreshed).  SGK (eq. 6): d = F x^T / (x x^T), normalised; X unchanged.
+   NSGK (Sec. 3, eq. 7): SGK on Z = Y + D X_prev - D X with the
+   representations X_prev the iteration started from (the previous
+   iteration's coding; the first iteration uses its own), so the users I_j and
+   the coefficients x come from X_prev and the group error is Z - D X_prev;
+   X unchanged.  dl_iterate keeps X_prev itself; a single update takes it as
+   an argument (dl_jau_update_nsgk). */
+typedef enum { DL_RULE_AKSVD = 0, DL_RULE_SGK = 1, DL_RULE_NSGK = 2 } dl_rule;
 
 typedef struct dl_params {
     int p, n, m, s;               /* signal size, atoms, signals, sparsity */
@@ -154,6 +160,19 @@ dl_status dl_csr(const dl_params *prm, const int32_t *X_idx, int32_t *row_ptr, i
 dl_status dl_jau_update(const dl_params *prm, const float *Y, float *D, const int32_t *X_idx,
                         float *X_val, void *ws, size_t ws_bytes, dl_stream_t stream);
 
+/* Step 2 with the NSGK rule (Sec. 3, eq. 7; prm->rule must be DL_RULE_NSGK):
+   the group loop of dl_jau_update on Z = Y + D X_prev - D X, where X
+   (X_idx/X_val) is this iteration's coding against D and X_prev
+   (Xprev_idx/Xprev_val, the same ELL layout) the previous one: the users of
+   every atom and their coefficients come from X_prev, the group error is
+   Z - D X_prev with the current D, and d_j = F x^T / (x x^T), normalised.
+   D is replaced by the new dictionary; neither X changes.  An atom X_prev
+   does not use keeps its value. */
+dl_status dl_jau_update_nsgk(const dl_params *prm, const float *Y, float *D,
+                             const int32_t *X_idx, const float *X_val,
+                             const int32_t *Xprev_idx, const float *Xprev_val, void *ws,
+                             size_t ws_bytes, dl_stream_t stream);
+
 /* rmse_out[0] = ||Y - D X||_F / sqrt(p m), accumulated in FP64 (the error the
    paper plots, Sec. 4.2).  rmse_out is a device pointer to one double. */
 dl_status dl_rmse(const dl_params *prm, const float *Y, const float *D, const int32_t *X_idx,
@@ -178,7 +197,8 @@ dl_status dl_rmse_noalloc(const dl_params *prm, const float *Y, const float *D,
    first) and the final dictionary on exit; X_idx/X_val hold the last
    iteration's representations after its update; rmse[k] (device, `iters`
    doubles) is the error after iteration k.  Zeroes the workspace counters
-   first. */
+   first.  With the NSGK rule the workspace also keeps the previous
+   iteration's representations. */
 dl_status dl_iterate(const dl_params *prm, const float *Y, float *D, int iters, int32_t *X_idx,
                      float *X_val, double *rmse, void *ws, size_t ws_bytes, dl_stream_t stream);
 
@@ -315,8 +335,8 @@ dl_status dl_iterate_proposed(const dl_params *prm, const dl_proposal *pr, const
    first; OMP runs one such launch per lane-group shape in use.  Each problem
    gets bit-for-bit the results of dl_iterate with the same parameters. */
 typedef struct dl_problem {
-    dl_params prm;    /* FP32 and group_size >= n only; rule, tolerances and OMP
-                         launch shape as for dl_iterate */
+    dl_params prm;    /* FP32, group_size >= n and the AK-SVD or SGK rule only;
+                         tolerances and OMP launch shape as for dl_iterate */
     const float *Y;   /* [m][p] signals (device, 16-byte aligned) */
     float *D;         /* [n][p] initial dictionary in, learned dictionary out
                          (rows are normalised first; device, 16-byte aligned) */

@@ -38,6 +38,12 @@ Layout layout_for(const dl_params &prm)
     L.atom_state = take(sizeof(int32_t) * n);
     L.partial = take(sizeof(float) * (size_t)max_chunks(prm) * p);
     L.rmse_part = take(sizeof(double) * (size_t)rmse_blocks(prm.m));
+    if (prm.rule == DL_RULE_NSGK) {
+        L.idx_prev = take(sizeof(int32_t) * m * s);
+        L.val_prev = take(sizeof(float) * m * s);
+    } else {
+        L.idx_prev = L.val_prev = 0;
+    }
     if (prm.precision == DL_PREC_BF16) {
         L.Dbf = take(sizeof(uint16_t) * n * p);
         L.Ybf = take(sizeof(uint16_t) * m * p);
@@ -73,7 +79,7 @@ bool valid_params(const dl_params *prm)
         return false;
     if (q.precision == DL_PREC_BF16 && q.p % 8 != 0)
         return false;
-    if (q.rule != DL_RULE_AKSVD && q.rule != DL_RULE_SGK)
+    if (q.rule != DL_RULE_AKSVD && q.rule != DL_RULE_SGK && q.rule != DL_RULE_NSGK)
         return false;
     if (!(q.pivot_fp64_threshold >= 0.f) || !(q.tol_corr >= 0.f) || !(q.tol_pivot >= 0.f))
         return false;
@@ -440,6 +446,8 @@ dl_status dl_jau_update(const dl_params *prm, const float *Y, float *D, const in
     dl_status rc = check_ws(prm, ws, ws_bytes, &w);
     if (rc != DL_OK)
         return rc;
+    if (prm->rule == DL_RULE_NSGK)
+        return DL_EINVAL;  // the previous representations are needed: dl_jau_update_nsgk
     hipStream_t st = (hipStream_t)stream;
     const dl_params &q = *prm;
     float *E = w.at<float>(w.L.E);
@@ -452,6 +460,36 @@ dl_status dl_jau_update(const dl_params *prm, const float *Y, float *D, const in
         return rc;
     DL_TRY(launch_copy(Dn, D, sizeof(float) * (size_t)q.n * q.p, st));
     DL_TRY(launch_copy(valn, X_val, sizeof(float) * (size_t)q.m * q.s, st));
+    return DL_OK;
+}
+
+dl_status dl_jau_update_nsgk(const dl_params *prm, const float *Y, float *D,
+                             const int32_t *X_idx, const float *X_val,
+                             const int32_t *Xprev_idx, const float *Xprev_val, void *ws,
+                             size_t ws_bytes, dl_stream_t stream)
+{
+    if (!valid_params(prm) || prm->rule != DL_RULE_NSGK || !aligned(Y, 16) || !aligned(D, 16) ||
+        !aligned(X_idx, 4) || !aligned(X_val, 4) || !aligned(Xprev_idx, 4) ||
+        !aligned(Xprev_val, 4))
+        return DL_EINVAL;
+    Ws w;
+    dl_status rc = check_ws(prm, ws, ws_bytes, &w);
+    if (rc != DL_OK)
+        return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const dl_params &q = *prm;
+    float *E = w.at<float>(w.L.E);
+    float *Dn = w.at<float>(w.L.Dn);
+    float *valn = w.at<float>(w.L.valn);
+    // The first group's error Z - D X_prev = Y - D X (eq. 7); the users and
+    // coefficients come from X_prev, whose coefficients the update keeps (the
+    // kernels treat every rule but AK-SVD alike), and later groups keep E equal
+    // to Z - D X_prev with the current D.
+    DL_TRY(launch_residual(Y, D, X_idx, X_val, E, q.p, q.n, q.m, q.s, st));
+    rc = run_update(q, Y, D, Dn, Xprev_idx, Xprev_val, valn, w, st);
+    if (rc != DL_OK)
+        return rc;
+    DL_TRY(launch_copy(Dn, D, sizeof(float) * (size_t)q.n * q.p, st));
     return DL_OK;
 }
 
@@ -505,24 +543,43 @@ static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, in
     // carried error needs that refresh, so it is used at group size n only.
     const bool one_group = q.group_size >= q.n;
     const bool defer = one_group && error_defer_ok(q.m);
+    // NSGK updates with the previous iteration's coding (eq. 7) and keeps X:
+    // the codings alternate between the caller's X and the workspace's
+    // previous-coding buffers, arranged so that the last one lands in X.
+    const bool nsgk = q.rule == DL_RULE_NSGK;
+    int32_t *idx_buf[2] = {X_idx, nsgk ? w.at<int32_t>(w.L.idx_prev) : nullptr};
+    float *val_buf[2] = {X_val, nsgk ? w.at<float>(w.L.val_prev) : nullptr};
     RmseArgs prev{};
     bool pending = false;
     for (int k = 0; k < iters; ++k) {
+        const int cb = (iters - 1 - k) & 1;
+        int32_t *idx_k = nsgk ? idx_buf[cb] : X_idx;
+        float *val_k = nsgk ? val_buf[cb] : val_ws;
         OmpExtra x;
         x.rnorm = rref;
         x.prev_err = pending ? &prev : nullptr;
-        rc = run_omp(q, Dcur, Y, X_idx, val_ws, w, st, x);
+        rc = run_omp(q, Dcur, Y, idx_k, val_k, w, st, x);
         if (rc != DL_OK)
             return rc;
         if (hist)
-            DL_TRY(launch_copy(X_idx, hist + (size_t)k * ms, 4 * ms, st));
-        rc = run_update(q, Y, Dcur, Dnext, X_idx, val_ws, X_val, w, st, pending ? &prev : nullptr,
-                        one_group);
+            DL_TRY(launch_copy(idx_k, hist + (size_t)k * ms, 4 * ms, st));
+        if (nsgk) {
+            // the users and coefficients of the previous coding (the first
+            // iteration's own); the update's kept coefficients go to scratch
+            const int32_t *idx_p = k == 0 ? idx_k : idx_buf[cb ^ 1];
+            const float *val_p = k == 0 ? val_k : val_buf[cb ^ 1];
+            rc = run_update(q, Y, Dcur, Dnext, idx_p, val_p, w.at<float>(w.L.valn), w, st,
+                            pending ? &prev : nullptr, one_group);
+        } else {
+            rc = run_update(q, Y, Dcur, Dnext, idx_k, val_k, X_val, w, st,
+                            pending ? &prev : nullptr, one_group);
+        }
         if (rc != DL_OK)
             return rc;
-        prev = rmse_args(q, Y, Dnext, X_idx, X_val, rmse + k, w);
+        float *xout = nsgk ? val_k : X_val;
+        prev = rmse_args(q, Y, Dnext, idx_k, xout, rmse + k, w);
         if (one_group)
-            add_refresh(prev, q, Dcur, val_ws, X_val, w);
+            add_refresh(prev, q, Dcur, val_k, xout, w);
         pending = defer;
         if (!defer)
             DL_TRY(launch_rmse(prev, st));
@@ -605,7 +662,7 @@ static bool proposal_ok(const dl_params *prm, const dl_proposal *pr, const void 
 {
     return pr && aligned(pr->cand, 4) && (pr->k == 8 || pr->k == 12 || pr->k == 16) &&
            pr->k >= prm->s && pr->margin >= 0.f && pr->audit_every >= 0 &&
-           prm->precision == DL_PREC_FP32 && aligned(pws, 256);
+           prm->precision == DL_PREC_FP32 && prm->rule != DL_RULE_NSGK && aligned(pws, 256);
 }
 
 dl_status dl_code_proposed(const dl_params *prm, const dl_proposal *pr, const float *D,

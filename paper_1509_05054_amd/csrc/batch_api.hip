@@ -67,7 +67,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool problem_ok(const dl_problem &pb)
 {
     const dl_params &q = pb.prm;
-    if (!params_ok(&q) || q.precision != DL_PREC_FP32 || q.group_size < q.n)
+    if (!params_ok(&q) || q.precision != DL_PREC_FP32 || q.group_size < q.n ||
+        q.rule == DL_RULE_NSGK)
         return false;
     auto al = [](const void *ptr, size_t a) { return ptr && ((uintptr_t)ptr % a) == 0; };
     return al(pb.Y, 16) && al(pb.D, 16) && al(pb.X_idx, 4) && al(pb.X_val, 4);
@@ -347,7 +348,8 @@ size_t dl_batch_workspace_size(const dl_problem *probs, int count)
         return 0;
     for (int b = 0; b < count; ++b) {
         const dl_params &q = probs[b].prm;
-        if (!params_ok(&q) || q.precision != DL_PREC_FP32 || q.group_size < q.n)
+        if (!params_ok(&q) || q.precision != DL_PREC_FP32 || q.group_size < q.n ||
+            q.rule == DL_RULE_NSGK)
             return 0;
     }
     return batch_layout(probs, count).total;

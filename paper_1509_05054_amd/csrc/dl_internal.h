@@ -50,6 +50,8 @@ struct Layout {
     size_t atom_state; // [n] int: 0 updated, 1 no users, 2 zero F x^T
     size_t partial;    // [max_chunks][p] float
     size_t rmse_part;  // [rmse_blocks(m)] double
+    size_t idx_prev;   // [m][s] int, previous coding (NSGK rule only)
+    size_t val_prev;   // [m][s] float, previous coding (NSGK rule only)
     size_t Dbf;        // [n][p] bf16 (precision variant)
     size_t Ybf;        // [m][p] bf16 (precision variant)
     size_t total;

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libdl_mi355.so")
 
 DL_OK, DL_EINVAL, DL_EWORKSPACE, DL_EHIP, DL_ENUMERIC, DL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PREC_FP32, PREC_BF16 = 0, 1
-RULE_AKSVD, RULE_SGK = 0, 1
+RULE_AKSVD, RULE_SGK, RULE_NSGK = 0, 1, 2
 
 
 class DLError(RuntimeError):
@@ -75,6 +75,8 @@ SIGNATURES = {
     "dl_omp": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "dl_csr": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "dl_jau_update": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "dl_jau_update_nsgk": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                          ctypes.c_size_t, _vp]),
     "dl_rmse": (ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "dl_iterate": (ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp]),
@@ -218,6 +220,13 @@ def csr(prm: Params, X_idx, row_ptr, users, ws, stream=None):
 def jau_update(prm: Params, Y, D, X_idx, X_val, ws, stream=None):
     _check(lib().dl_jau_update(prm.ref(), _ptr(Y), _ptr(D), _ptr(X_idx), _ptr(X_val), _ptr(ws),
                                ws.numel(), _stream(stream)), "dl_jau_update")
+
+
+def jau_update_nsgk(prm: Params, Y, D, X_idx, X_val, Xprev_idx, Xprev_val, ws, stream=None):
+    """NSGK atom update of D (eq. 7) from this coding X and the previous one."""
+    _check(lib().dl_jau_update_nsgk(prm.ref(), _ptr(Y), _ptr(D), _ptr(X_idx), _ptr(X_val),
+                                    _ptr(Xprev_idx), _ptr(Xprev_val), _ptr(ws), ws.numel(),
+                                    _stream(stream)), "dl_jau_update_nsgk")
 
 
 def rmse(prm: Params, Y, D, X_idx, X_val, out, ws, stream=None):
