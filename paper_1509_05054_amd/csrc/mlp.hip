@@ -153,23 +153,30 @@ __global__ void sum_splits_kernel(const float *__restrict__ part, float *__restr
     }
 }
 
-// out[r] = sum_c X[r][c] for a BF16 matrix X[rows][cols] (one wave per row)
+// out[r] = sum_c X[r][c] for a BF16 matrix X[rows][cols] (cols % 8 == 0): one
+// workgroup per row, 16-byte loads (8 values per lane per load), the lane
+// partials summed in a fixed order (wave shuffles, then the four waves).
 __global__ __launch_bounds__(256) void rowsum_bf16_kernel(const uint16_t *__restrict__ X,
                                                           float *__restrict__ out, int rows,
                                                           int cols)
 {
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= rows)
-        return;
+    __shared__ float red[4];
+    const int row = blockIdx.x;
+    const uint16_t *x = X + (size_t)row * cols;
     float acc = 0.f;
-    for (int c = lane; c < cols; c += 64)
-        acc += bf2f(X[(size_t)row * cols + c]);
+    for (int c = 8 * threadIdx.x; c < cols; c += 8 * 256) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(x + c);
+        acc += bf2f(v.x & 0xffff) + bf2f(v.x >> 16) + bf2f(v.y & 0xffff) + bf2f(v.y >> 16) +
+               bf2f(v.z & 0xffff) + bf2f(v.z >> 16) + bf2f(v.w & 0xffff) + bf2f(v.w >> 16);
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
         acc += __shfl_xor(acc, off);
-    if (lane == 0)
-        out[row] = acc;
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        out[row] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // 1 / ||row|| in FP32 for one wave's row (0 for a zero row); every lane gets it.
@@ -320,9 +327,10 @@ hipError_t launch_sum_splits(const float *part, float *out, size_t count, int sp
 
 hipError_t launch_rowsum_bf16(const uint16_t *X, float *out, int rows, int cols, hipStream_t st)
 {
+    if (cols % 8 != 0)
+        return hipErrorInvalidValue;  // every caller passes the batch size, a multiple of 32
     prof_begin(DL_K_MLP, st);
-    hipLaunchKernelGGL(rowsum_bf16_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, X, out, rows,
-                       cols);
+    hipLaunchKernelGGL(rowsum_bf16_kernel, dim3(rows), dim3(256), 0, st, X, out, rows, cols);
     prof_end(DL_K_MLP, st);
     return hipGetLastError();
 }

@@ -106,20 +106,59 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Lower-triangle storage index of entry (r, q), r >= q.
+__host__ __device__ constexpr int tri(int r, int q) { return r * (r + 1) / 2 + q; }
+
+// Cholesky factor of the masked K2 x K2 matrix (entries of dead atoms replaced
+// by those of the identity), with reciprocal diagonals; ok becomes false on a
+// non-positive pivot (that pivot is then taken as 1).
+template <int K2>
+__device__ inline void masked_cholesky(const float *Gc, const bool *alive, float *L, float *rd,
+                                       bool &ok)
+{
+#pragma unroll
+    for (int r = 0; r < K2; ++r)
+#pragma unroll
+        for (int q = 0; q <= r; ++q) {
+            float acc = (alive[r] && alive[q]) ? Gc[tri(r, q)] : (r == q ? 1.f : 0.f);
+#pragma unroll
+            for (int t = 0; t < q; ++t)
+                acc -= L[tri(r, t)] * L[tri(q, t)];
+            if (r == q) {
+                if (!(acc > 0.f)) {
+                    ok = false;
+                    acc = 1.f;
+                }
+                L[tri(r, r)] = sqrtf(acc);
+                rd[r] = 1.0f / L[tri(r, r)];
+            } else {
+                L[tri(r, q)] = acc * rd[q];
+            }
+        }
+}
+
 // One thread per signal.  K2 candidates: correlations b = D_C^T y and Gram
 // entries G_C from the atoms' Gram matrix; least squares on the candidates;
-// backward elimination to s atoms: each round refits on the surviving set and
-// drops the atom with the smallest c_j^2 / [(G_C)^{-1}]_jj (ties: lower atom
-// index).  Eliminated atoms are masked (their rows and columns of G_C become
-// those of the identity), so no array is ever indexed by a run-time value.
-// The residual e = y - D_S x is formed explicitly; the signal goes back to
-// OMP when ||e|| > (1 + margin) * rref.
+// backward elimination to s atoms: drop the atom with the smallest
+// c_j^2 / [(G_C)^{-1}]_jj (ties: lower atom index) until s remain.
+// The inverse W = (G_C)^{-1} is formed once from the Cholesky factor; each
+// removal of atom j then updates it and the solution in O(K2^2):
+//     W <- W - W e_j e_j^T W / W_jj,   c <- c - W e_j c_j / W_jj,
+// which are the inverse and the least-squares solution of the remaining set
+// (the removed row and column become zero).  The survivors' coefficients are
+// finally refitted by a fresh Cholesky solve.  Runtime indices select with
+// masks, so no register array is indexed by a run-time value.  The residual
+// e = y - D_S x is formed explicitly; the signal goes back to OMP when
+// ||e|| > (1 + margin) * rref.
 template <int K2>
 __global__ __launch_bounds__(256) void ls_prune_kernel(ProposeArgs a)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m)
-        return;
+    constexpr int NT = K2 * (K2 + 1) / 2;
+    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x * blockDim.x + (threadIdx.x & ~63) >= a.m)
+        return;  // the whole wave (the fallback list below is filled per wave)
+    const bool valid = i0 < a.m;
+    const int i = valid ? i0 : a.m - 1;  // lanes past the end redo the last signal, store nothing
     const int p = a.p, s = a.s, n = a.n, ldn = a.ldn;
     int c[K2];
     bool alive[K2];
@@ -143,89 +182,126 @@ __global__ __launch_bounds__(256) void ls_prune_kernel(ProposeArgs a)
             b[t] += d[0] * y[0] + d[1] * y[1] + d[2] * y[2] + d[3] * y[3];
         }
     }
+#pragma unroll
+    for (int t = 0; t < K2; ++t)
+        if (!alive[t])
+            b[t] = 0.f;
     // Gram entries (lower triangle)
-    float Gc[K2 * (K2 + 1) / 2];
+    float Gc[NT];
 #pragma unroll
     for (int r = 0; r < K2; ++r)
 #pragma unroll
         for (int q = 0; q <= r; ++q)
-            Gc[r * (r + 1) / 2 + q] = a.G[(size_t)c[r] * ldn + c[q]];
+            Gc[tri(r, q)] = a.G[(size_t)c[r] * ldn + c[q]];
 
     int kept = 0;
 #pragma unroll
     for (int t = 0; t < K2; ++t)
         kept += alive[t] ? 1 : 0;
-    float x[K2];
     bool ok = true;
-    for (int round = 0;; ++round) {
-        // Cholesky of the masked G_C
-        float L[K2 * (K2 + 1) / 2];
+    float x[K2];
+    if (kept > s) {
+        // W = L^{-T} L^{-1}: first M = L^{-1} (lower), then W_rq = sum_t M_tr M_tq
+        float L[NT], rd[K2];
+        masked_cholesky<K2>(Gc, alive, L, rd, ok);
+        float Mi[NT];
+#pragma unroll
+        for (int q = 0; q < K2; ++q) {
+            Mi[tri(q, q)] = rd[q];
+#pragma unroll
+            for (int r = q + 1; r < K2; ++r) {
+                float acc = 0.f;
+#pragma unroll
+                for (int t = q; t < r; ++t)
+                    acc += L[tri(r, t)] * Mi[tri(t, q)];
+                Mi[tri(r, q)] = -acc * rd[r];
+            }
+        }
+        float W[NT];
 #pragma unroll
         for (int r = 0; r < K2; ++r)
 #pragma unroll
             for (int q = 0; q <= r; ++q) {
-                float acc = (alive[r] && alive[q]) ? Gc[r * (r + 1) / 2 + q] : (r == q ? 1.f : 0.f);
+                float acc = 0.f;
 #pragma unroll
-                for (int t = 0; t < q; ++t)
-                    acc -= L[r * (r + 1) / 2 + t] * L[q * (q + 1) / 2 + t];
-                if (r == q) {
-                    if (!(acc > 0.f)) {
-                        ok = false;
-                        acc = 1.f;
-                    }
-                    L[r * (r + 1) / 2 + r] = sqrtf(acc);
-                } else {
-                    L[r * (r + 1) / 2 + q] = acc / L[q * (q + 1) / 2 + q];
-                }
+                for (int t = r; t < K2; ++t)
+                    acc += Mi[tri(t, r)] * Mi[tri(t, q)];
+                W[tri(r, q)] = acc;
             }
-        // x = G_C^{-1} b (masked entries of b are 0)
+#pragma unroll
+        for (int r = 0; r < K2; ++r) {
+            float acc = 0.f;
+#pragma unroll
+            for (int q = 0; q < K2; ++q)
+                acc += W[r >= q ? tri(r, q) : tri(q, r)] * b[q];
+            x[r] = acc;
+        }
+        while (kept > s) {
+            // the removal that raises the residual least
+            float best = INFINITY;
+            int batom = 0x7fffffff;
+            bool oh[K2];
+#pragma unroll
+            for (int j = 0; j < K2; ++j) {
+                const float cost = x[j] * x[j] / W[tri(j, j)];
+                const bool better = alive[j] && (cost < best || (cost == best && c[j] < batom));
+                best = better ? cost : best;
+                batom = better ? c[j] : batom;
+            }
+            float wjj = 1.f, xj = 0.f;
+#pragma unroll
+            for (int j = 0; j < K2; ++j) {
+                oh[j] = alive[j] && c[j] == batom;
+                wjj = oh[j] ? W[tri(j, j)] : wjj;
+                xj = oh[j] ? x[j] : xj;
+            }
+            // column j of W (by mask), then the rank-one downdate
+            float col[K2];
+#pragma unroll
+            for (int r = 0; r < K2; ++r) {
+                float v = 0.f;
+#pragma unroll
+                for (int j = 0; j < K2; ++j)
+                    v = oh[j] ? W[r >= j ? tri(r, j) : tri(j, r)] : v;
+                col[r] = v;
+            }
+            const float inv = 1.0f / wjj;
+            const float f = xj * inv;
+#pragma unroll
+            for (int r = 0; r < K2; ++r) {
+                x[r] -= col[r] * f;
+                const float cr = col[r] * inv;
+#pragma unroll
+                for (int q = 0; q <= r; ++q)
+                    W[tri(r, q)] -= cr * col[q];
+            }
+#pragma unroll
+            for (int j = 0; j < K2; ++j)
+                alive[j] = alive[j] && !oh[j];
+            --kept;
+        }
+    }
+    {
+        // least squares on the survivors: a fresh masked Cholesky solve
+        float L[NT], rd[K2];
+        masked_cholesky<K2>(Gc, alive, L, rd, ok);
         float z[K2];
 #pragma unroll
         for (int r = 0; r < K2; ++r) {
             float acc = alive[r] ? b[r] : 0.f;
 #pragma unroll
             for (int t = 0; t < r; ++t)
-                acc -= L[r * (r + 1) / 2 + t] * z[t];
-            z[r] = acc / L[r * (r + 1) / 2 + r];
+                acc -= L[tri(r, t)] * z[t];
+            z[r] = acc * rd[r];
         }
 #pragma unroll
         for (int r = K2 - 1; r >= 0; --r) {
             float acc = z[r];
 #pragma unroll
             for (int t = r + 1; t < K2; ++t)
-                acc -= L[t * (t + 1) / 2 + r] * x[t];
-            x[r] = acc / L[r * (r + 1) / 2 + r];
+                acc -= L[tri(t, r)] * x[t];
+            x[r] = acc * rd[r];
         }
-        if (kept <= s)
-            break;
-        // removal costs: [(G_C)^{-1}]_jj = || L^{-1} e_j ||^2
-        float best = INFINITY;
-        int bj = -1, batom = 0x7fffffff;
-#pragma unroll
-        for (int j = 0; j < K2; ++j) {
-            float w[K2];
-            float dj = 0.f;
-#pragma unroll
-            for (int r = j; r < K2; ++r) {
-                float acc = r == j ? 1.f : 0.f;
-#pragma unroll
-                for (int t = j; t < r; ++t)
-                    acc -= L[r * (r + 1) / 2 + t] * w[t];
-                w[r] = acc / L[r * (r + 1) / 2 + r];
-                dj += w[r] * w[r];
-            }
-            const float cost = x[j] * x[j] / dj;
-            if (alive[j] && (cost < best || (cost == best && c[j] < batom))) {
-                best = cost;
-                bj = j;
-                batom = c[j];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < K2; ++j)
-            if (j == bj)
-                alive[j] = false;
-        --kept;
     }
 
     // explicit residual and the fallback test
@@ -236,27 +312,41 @@ __global__ __launch_bounds__(256) void ls_prune_kernel(ProposeArgs a)
         for (int t = 0; t < K2; ++t)
             if (alive[t])
                 e -= *reinterpret_cast<const f32x4 *>(a.D + (size_t)c[t] * p + q) * x[t];
-        *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e;
+        if (valid)
+            *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e;
         enorm2 += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + e[3] * e[3];
     }
-    int slot = 0;
+    if (valid) {
+        int slot = 0;
 #pragma unroll
-    for (int t = 0; t < K2; ++t)
-        if (alive[t] && slot < s) {
-            a.idx[(size_t)i * s + slot] = c[t];
-            a.val[(size_t)i * s + slot] = x[t];
-            ++slot;
+        for (int t = 0; t < K2; ++t)
+            if (alive[t] && slot < s) {
+                a.idx[(size_t)i * s + slot] = c[t];
+                a.val[(size_t)i * s + slot] = x[t];
+                ++slot;
+            }
+        for (int t = slot; t < s; ++t) {
+            a.idx[(size_t)i * s + t] = -1;
+            a.val[(size_t)i * s + t] = 0.f;
         }
-    for (int t = slot; t < s; ++t) {
-        a.idx[(size_t)i * s + t] = -1;
-        a.val[(size_t)i * s + t] = 0.f;
     }
+    // The rejected signals of the wave take consecutive places of the
+    // fallback list: one atomic per wave (a per-signal atomic on the one
+    // counter serialises most of the launch when most signals fall back).
+    // The list order only decides where OMP codes a signal, not its result.
     const float enorm = sqrtf(enorm2);
-    if (!ok || !(enorm <= (1.f + a.margin) * a.rref[i])) {
-        const int pos = atomicAdd(a.fb_count, 1);
-        a.fb_list[pos] = i;
-        atomicAdd(&a.ctl->fallbacks, 1ull);
+    const bool fb = valid && (!ok || !(enorm <= (1.f + a.margin) * a.rref[i]));
+    const unsigned long long mask = __ballot(fb);
+    const int lane = threadIdx.x & 63;
+    const int cnt = __popcll(mask);
+    int base = 0;
+    if (lane == 0 && cnt > 0) {
+        base = atomicAdd(a.fb_count, cnt);
+        atomicAdd(&a.ctl->fallbacks, (unsigned long long)cnt);
     }
+    base = __shfl(base, 0);
+    if (fb)
+        a.fb_list[base + __popcll(mask & ((1ull << lane) - 1ull))] = i;
 }
 
 // rows[k] = src[list[k]] for k < *count (p floats per row)

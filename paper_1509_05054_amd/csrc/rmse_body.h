@@ -190,29 +190,43 @@ __device__ inline void rmse_refresh_body(const RmseArgs &a, int blk, int nblk)
                 ey[u] = on[u] ? load4(a.Y + (size_t)(i0 + il) * p, q, p) : zero;
                 eo[u] = on[u] ? load4(a.E + (size_t)(i0 + il) * p, q, p) : zero;
             }
-            for (int t = 0; t < s; ++t) {
-                f32x4 dn[RU], dd[RU];
-                float x[RU];
-                int kp[RU];
+            // TS slots at a time: all their atom rows (old and new) are
+            // loaded before any is used, so the loads are in flight together
+            // (the stores of x' between them would otherwise order each
+            // slot's loads after the previous slot's store)
+            constexpr int TS = 4;
+            for (int t0 = 0; t0 < s; t0 += TS) {
+                f32x4 dn[RU][TS], dd[RU][TS];
+                float x[RU][TS];
+                int kp[RU][TS];
 #pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const int r = ilc[u] * s + t;
-                    const int j = sIdx[r];
-                    x[u] = on[u] ? sVal[r] : 0.f;
-                    kp[u] = on[u] ? sKeep[r] : 1;
-                    dn[u] = load4(a.D + (size_t)j * p, q, p);
-                    dd[u] = load4(a.Dold + (size_t)j * p, q, p);
-                }
+                for (int u = 0; u < RU; ++u)
 #pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const f32x4 f = eo[u] + dd[u] * x[u];
-                    float part = f[0] * dn[u][0] + f[1] * dn[u][1] + f[2] * dn[u][2] + f[3] * dn[u][3];
-                    for (int off = 1; off < lpu; off <<= 1)
-                        part += __shfl_xor(part, off);
-                    const float xn = kp[u] ? x[u] : part;
-                    if (on[u] && (lane % lpu) == 0)
-                        a.valn[(size_t)(i0 + ilc[u]) * s + t] = xn;
-                    ey[u] -= dn[u] * xn;
+                    for (int v = 0; v < TS; ++v) {
+                        const int t = t0 + v < s ? t0 + v : t0;
+                        const int r = ilc[u] * s + t;
+                        const int j = sIdx[r];
+                        x[u][v] = on[u] ? sVal[r] : 0.f;
+                        kp[u][v] = on[u] ? sKeep[r] : 1;
+                        dn[u][v] = load4(a.D + (size_t)j * p, q, p);
+                        dd[u][v] = load4(a.Dold + (size_t)j * p, q, p);
+                    }
+#pragma unroll
+                for (int v = 0; v < TS; ++v) {
+                    if (t0 + v >= s)
+                        break;  // uniform over the workgroup
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        const f32x4 f = eo[u] + dd[u][v] * x[u][v];
+                        float part = f[0] * dn[u][v][0] + f[1] * dn[u][v][1] +
+                                     f[2] * dn[u][v][2] + f[3] * dn[u][v][3];
+                        for (int off = 1; off < lpu; off <<= 1)
+                            part += __shfl_xor(part, off);
+                        const float xn = kp[u][v] ? x[u][v] : part;
+                        if (on[u] && (lane % lpu) == 0)
+                            a.valn[(size_t)(i0 + ilc[u]) * s + t0 + v] = xn;
+                        ey[u] -= dn[u][v] * xn;
+                    }
                 }
             }
 #pragma unroll

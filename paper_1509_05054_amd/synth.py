@@ -239,7 +239,8 @@ def batched_problems(count: int, seed: int, m_scale: float = 1.0):
     """Uneven independent problems: p in {16,36,64,144,256}, n = 2p or 4p,
     s ~ U{3..16} (capped at p), m log-uniform in [2048, 65536] (times m_scale).
 
-    Each problem draws patches from 4 synthetic images of its own.  Returns a
+    Each problem draws patches from 4 synthetic 512x512 images of its own (the
+    generator and image size of the other patch workloads).  Returns a
     list of dicts with keys p, n, s, m, Y, D0.
     """
     rng = np.random.default_rng(seed)
@@ -250,7 +251,7 @@ def batched_problems(count: int, seed: int, m_scale: float = 1.0):
         s = min(int(rng.integers(3, 17)), p)
         m = int(round(math.exp(rng.uniform(math.log(2048), math.log(65536)))))
         m = max(int(round(m * m_scale)), n)
-        imgs = synthetic_images(4, 256, seed * 1000 + b)
+        imgs = synthetic_images(4, 512, seed * 1000 + b)
         Y = image_patches(imgs, int(round(math.sqrt(p))), m, seed * 1000 + b + 1)
         D0 = initial_dictionary(Y, n, seed * 1000 + b + 2)
         out.append(dict(p=p, n=n, s=s, m=m, Y=Y, D0=D0))
