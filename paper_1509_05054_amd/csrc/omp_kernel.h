@@ -63,7 +63,8 @@ __device__ inline int dpp_all(int v)
 // (selects, no branch).
 __device__ inline void take_better(float &v, int &ix, float ov, int oi)
 {
-    const bool b = ov > v || (ov == v && oi < ix);
+    // bitwise, not short-circuit, operators: one mask, no branch
+    const bool b = (ov > v) | ((ov == v) & (oi < ix));
     v = b ? ov : v;
     ix = b ? oi : ix;
 }
@@ -347,18 +348,16 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         ck *= inv;
 
         // 4. u_k and the correlation update (not needed after the last step)
-        if (ok && k + 1 < s) {
-            vec_t<NPL> unew = g;
+        // (u_k is formed in its own registers: k is a compile-time constant)
+        if constexpr (k < US) {
+            if (ok && k + 1 < s) {
+                u[k] = g;
 #pragma unroll
-            for (int t = 0; t < US; ++t)
-                if (t < k)
-                    unew -= w[t] * u[t];
-            unew *= inv;
-            alpha -= ck * unew;
-#pragma unroll
-            for (int t = 0; t < US; ++t)
-                if (t == k)
-                    u[t] = unew;
+                for (int t = 0; t < k; ++t)
+                    u[k] -= w[t] * u[t];
+                u[k] *= inv;
+                alpha -= ck * u[k];
+            }
         }
         if (ok) {
             if (wsub * LPS + l == j / NPL)  // the lane holding atom j
@@ -465,25 +464,41 @@ __global__ __launch_bounds__(128) void omp_pair_kernel(OmpArgs a)
     omp_signals<64, NPL, SMAX, 2>(a, (int)blockIdx.x, m_eff);
 }
 
-// Batched problems of one launch shape: every wave takes items (GPW signals
-// of one problem) from the queue until none are left.
+// Batched problems of one launch shape: every wave takes tickets from the
+// queue until none are left; a ticket is `per_ticket` consecutive items of
+// the launch's item list (an item is GPW signals of one problem), so the
+// one counter sees a few atomics per wave rather than one per item (with
+// hundreds of thousands of small items the atomics on one address serialise).
 template <int LPS, int NPL, int SMAX>
 __global__ __launch_bounds__(64 * kWaves) void omp_batched_kernel(const OmpArgs *__restrict__ tab,
-                                                                  BatchList bl)
+                                                                  BatchList bl, int per_ticket)
 {
     constexpr int GPW = 64 / LPS;
     const int lane = threadIdx.x & 63;
     const int total = bl.start[bl.count];
     for (;;) {
-        int it = 0;
+        int tk = 0;
         if (lane == 0)
-            it = (int)atomicAdd(&bl.q->ticket, 1u);
-        it = __builtin_amdgcn_readfirstlane(it);  // lane 0's ticket, wave-uniform
-        if (it >= total)
+            tk = (int)atomicAdd(&bl.q->ticket, 1u);
+        tk = __builtin_amdgcn_readfirstlane(tk);  // lane 0's ticket, wave-uniform
+        const long long first = (long long)tk * per_ticket;
+        if (first >= total)
             break;
-        const int b = batch_find(bl.start, bl.count, it);
-        const OmpArgs a = tab[b];
-        omp_signals<LPS, NPL, SMAX>(a, (it - bl.start[b]) * GPW, a.m);
+        const int end = (int)min((long long)total, first + per_ticket);
+        // consecutive items mostly belong to one problem: its index, item range
+        // and arguments are looked up again only when an item leaves that range
+        int b = batch_find(bl.start, bl.count, (int)first);
+        int b0 = bl.start[b], b1 = bl.start[b + 1];
+        OmpArgs a = tab[b];
+        for (int it = (int)first; it < end; ++it) {
+            if (it >= b1) {
+                b = batch_find(bl.start, bl.count, it);
+                b0 = bl.start[b];
+                b1 = bl.start[b + 1];
+                a = tab[b];
+            }
+            omp_signals<LPS, NPL, SMAX>(a, (it - b0) * GPW, a.m);
+        }
     }
     if (lane == 0)
         batch_leave(bl.q, gridDim.x * kWaves);
@@ -495,9 +510,13 @@ hipError_t launch_omp_batched_t(const OmpArgs *tab, const BatchList &bl, int ite
 {
     const int wg = batch_workers((const void *)omp_batched_kernel<LPS, NPL, SMAX>, 64 * kWaves, 0,
                                  (items + kWaves - 1) / kWaves);
+    // about 16 tickets per wave, at most 8 items each
+    const long long waves = (long long)wg * kWaves;
+    int per = (int)(items / (16 * waves));
+    per = per < 1 ? 1 : (per > 8 ? 8 : per);
     prof_begin(DL_K_OMP, st);
     hipLaunchKernelGGL((omp_batched_kernel<LPS, NPL, SMAX>), dim3(wg), dim3(64 * kWaves), 0, st,
-                       tab, bl);
+                       tab, bl, per);
     prof_end(DL_K_OMP, st);
     return hipGetLastError();
 }

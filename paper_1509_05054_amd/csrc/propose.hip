@@ -129,224 +129,286 @@ __device__ inline void masked_cholesky(const float *Gc, const bool *alive, float
                     ok = false;
                     acc = 1.f;
                 }
-                L[tri(r, r)] = sqrtf(acc);
-                rd[r] = 1.0f / L[tri(r, r)];
+                // hardware square root and reciprocal (1 ulp): the pruning's
+                // decisions are checked for validity, not bit for bit
+                L[tri(r, r)] = __builtin_amdgcn_sqrtf(acc);
+                rd[r] = __builtin_amdgcn_rcpf(L[tri(r, r)]);
             } else {
                 L[tri(r, q)] = acc * rd[q];
             }
         }
 }
 
-// One thread per signal.  K2 candidates: correlations b = D_C^T y and Gram
-// entries G_C from the atoms' Gram matrix; least squares on the candidates;
-// backward elimination to s atoms: drop the atom with the smallest
-// c_j^2 / [(G_C)^{-1}]_jj (ties: lower atom index) until s remain.
-// The inverse W = (G_C)^{-1} is formed once from the Cholesky factor; each
-// removal of atom j then updates it and the solution in O(K2^2):
-//     W <- W - W e_j e_j^T W / W_jj,   c <- c - W e_j c_j / W_jj,
-// which are the inverse and the least-squares solution of the remaining set
-// (the removed row and column become zero).  The survivors' coefficients are
-// finally refitted by a fresh Cholesky solve.  Runtime indices select with
-// masks, so no register array is indexed by a run-time value.  The residual
-// e = y - D_S x is formed explicitly; the signal goes back to OMP when
-// ||e|| > (1 + margin) * rref.
-template <int K2>
-__global__ __launch_bounds__(256) void ls_prune_kernel(ProposeArgs a)
+// Sum over the groups of LPU consecutive lanes (every lane gets its group's
+// sum): DPP moves inside rows of 16 lanes, shuffles across rows.
+template <int LPU>
+__device__ inline float lane_group_sum(float v)
 {
-    constexpr int NT = K2 * (K2 + 1) / 2;
-    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x * blockDim.x + (threadIdx.x & ~63) >= a.m)
-        return;  // the whole wave (the fallback list below is filled per wave)
-    const bool valid = i0 < a.m;
-    const int i = valid ? i0 : a.m - 1;  // lanes past the end redo the last signal, store nothing
-    const int p = a.p, s = a.s, n = a.n, ldn = a.ldn;
-    int c[K2];
-    bool alive[K2];
-#pragma unroll
-    for (int t = 0; t < K2; ++t) {
-        c[t] = a.cand[(size_t)i * K2 + t];
-        alive[t] = c[t] >= 0 && c[t] < n;
-        if (!alive[t])
-            c[t] = 0;
-    }
-    // correlations with the candidates
-    float b[K2];
-#pragma unroll
-    for (int t = 0; t < K2; ++t)
-        b[t] = 0.f;
-    for (int q = 0; q < p; q += 4) {
-        const f32x4 y = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
-#pragma unroll
-        for (int t = 0; t < K2; ++t) {
-            const f32x4 d = *reinterpret_cast<const f32x4 *>(a.D + (size_t)c[t] * p + q);
-            b[t] += d[0] * y[0] + d[1] * y[1] + d[2] * y[2] + d[3] * y[3];
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < K2; ++t)
-        if (!alive[t])
-            b[t] = 0.f;
-    // Gram entries (lower triangle)
-    float Gc[NT];
-#pragma unroll
-    for (int r = 0; r < K2; ++r)
-#pragma unroll
-        for (int q = 0; q <= r; ++q)
-            Gc[tri(r, q)] = a.G[(size_t)c[r] * ldn + c[q]];
+    if constexpr (LPU >= 2)
+        v += __int_as_float(dpp<0xB1>(__float_as_int(v)));   // lane ^ 1
+    if constexpr (LPU >= 4)
+        v += __int_as_float(dpp<0x4E>(__float_as_int(v)));   // lane ^ 2
+    if constexpr (LPU >= 8)
+        v += __int_as_float(dpp<0x141>(__float_as_int(v)));  // half-row mirror
+    if constexpr (LPU >= 16)
+        v += __int_as_float(dpp<0x140>(__float_as_int(v)));  // row mirror
+    if constexpr (LPU >= 32)
+        v += __shfl_xor(v, 16);
+    if constexpr (LPU >= 64)
+        v += __shfl_xor(v, 32);
+    return v;
+}
 
-    int kept = 0;
+// The learned coding, a block of kPruneBlock signals at a time per
+// workgroup (persistent over the blocks), in three phases:
+//  1. (LPU lanes per signal, one float4 of the signal per lane, so the loads
+//     of y and of the candidate atoms are whole row segments) the
+//     correlations b_t = d_{c_t}^T y of the K2 candidates, to LDS.  When the
+//     dictionary fits (n p <= kPruneLdsFloats) it is staged in LDS once per
+//     workgroup, and the candidate rows of phases 1 and 3 are read from there:
+//     every signal reads K2 rows, which from L2 would be 3 KB per signal;
+//  2. (one thread per signal) least squares on the candidates and backward
+//     elimination to s atoms: drop the atom with the smallest
+//     c_j^2 / [(G_C)^{-1}]_jj (ties: lower atom index) until s remain.  The
+//     inverse W = (G_C)^{-1} is formed once from the Cholesky factor of the
+//     Gram entries G_C; each removal of atom j then updates it and the
+//     solution in O(K2^2):
+//         W <- W - W e_j e_j^T W / W_jj,   c <- c - W e_j c_j / W_jj,
+//     which are the inverse and the least-squares solution of the remaining
+//     set (the removed row and column become zero), so the survivors'
+//     coefficients are their least-squares solution without a refit.
+//     Runtime indices select with masks, so no register array is indexed by
+//     a run-time value;
+//  3. (LPU lanes per signal again) the residual e = y - D_S x, written to E,
+//     and the fallback test: the signal goes back to OMP when
+//     ||e|| > (1 + margin) * rref.  A block's rejected signals are gathered
+//     in LDS and take consecutive places of the fallback list with one
+//     atomic per block (one per signal or per wave serialises on the single
+//     counter when most signals fall back); the list order decides only
+//     where OMP codes a signal, not its result.
+constexpr int kPruneBlock = 512;        // signals per block (8 waves)
+constexpr int kPruneLdsFloats = 16384;  // dictionaries up to 64 KB are staged in LDS
+constexpr int kPruneSlots = 32;         // LDS floats per signal: b, then (atom, x) pairs
+
+template <int K2, int LPU, bool DLDS>
+__global__ __launch_bounds__(kPruneBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void ls_prune_kernel(ProposeArgs a)
+{
+    static_assert(2 * K2 <= kPruneSlots, "LDS slots per signal");
+    constexpr int NT = K2 * (K2 + 1) / 2;
+    constexpr int GPW = 64 / LPU;          // signals per wave in phases 1 and 3
+    constexpr int NW = kPruneBlock / 64;   // waves per workgroup
+    __shared__ float sD[DLDS ? kPruneLdsFloats : 1];
+    __shared__ float sBX[kPruneBlock * kPruneSlots];
+    __shared__ int sOk[kPruneBlock];
+    __shared__ int sFb[kPruneBlock];
+    __shared__ int sFbCount, sFbBase;
+    const int p = a.p, s = a.s, n = a.n, ldn = a.ldn;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (DLDS) {
+        for (int e = 4 * tid; e < n * p; e += 4 * kPruneBlock)
+            *reinterpret_cast<f32x4 *>(sD + e) = *reinterpret_cast<const f32x4 *>(a.D + e);
+    }
+    const float *Dr = DLDS ? sD : a.D;  // rows of the dictionary for phases 1 and 3
+    const int g = lane / LPU, l = lane % LPU, q = 4 * l;
+    const f32x4 zero = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nblocks = (a.m + kPruneBlock - 1) / kPruneBlock;
+    for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const int i0 = blk * kPruneBlock;
+        const int nsig = min(kPruneBlock, a.m - i0);
+        if (tid == 0)
+            sFbCount = 0;
+        __syncthreads();  // the dictionary is staged; the previous block is done
+
+        // ---- phase 1: candidate correlations
+        for (int il0 = wave * GPW; il0 < kPruneBlock; il0 += NW * GPW) {
+            const int il = il0 + g;
+            const bool on = il < nsig;
+            const f32x4 y = (on && q < p)
+                                ? *reinterpret_cast<const f32x4 *>(a.Y + (size_t)(i0 + il) * p + q)
+                                : zero;
+            float part[K2];
 #pragma unroll
-    for (int t = 0; t < K2; ++t)
-        kept += alive[t] ? 1 : 0;
-    bool ok = true;
-    float x[K2];
-    if (kept > s) {
-        // W = L^{-T} L^{-1}: first M = L^{-1} (lower), then W_rq = sum_t M_tr M_tq
-        float L[NT], rd[K2];
-        masked_cholesky<K2>(Gc, alive, L, rd, ok);
-        float Mi[NT];
-#pragma unroll
-        for (int q = 0; q < K2; ++q) {
-            Mi[tri(q, q)] = rd[q];
-#pragma unroll
-            for (int r = q + 1; r < K2; ++r) {
-                float acc = 0.f;
-#pragma unroll
-                for (int t = q; t < r; ++t)
-                    acc += L[tri(r, t)] * Mi[tri(t, q)];
-                Mi[tri(r, q)] = -acc * rd[r];
+            for (int t = 0; t < K2; ++t) {
+                int c = on ? a.cand[(size_t)(i0 + il) * K2 + t] : -1;
+                c = (c >= 0 && c < n) ? c : -1;
+                const f32x4 d =
+                    (c >= 0 && q < p) ? *reinterpret_cast<const f32x4 *>(Dr + (size_t)c * p + q) : zero;
+                part[t] = d[0] * y[0] + d[1] * y[1] + d[2] * y[2] + d[3] * y[3];
             }
+#pragma unroll
+            for (int t = 0; t < K2; ++t)
+                part[t] = lane_group_sum<LPU>(part[t]);
+            if (on && l == 0)
+#pragma unroll
+                for (int t = 0; t < K2; ++t)
+                    sBX[il * kPruneSlots + t] = part[t];
         }
-        float W[NT];
+        __syncthreads();
+
+        // ---- phase 2: least squares and backward elimination, one thread per signal
+        if (tid < nsig) {
+            const int i = i0 + tid;
+            int c[K2];
+            bool alive[K2];
+            float b[K2];
 #pragma unroll
-        for (int r = 0; r < K2; ++r)
-#pragma unroll
-            for (int q = 0; q <= r; ++q) {
-                float acc = 0.f;
-#pragma unroll
-                for (int t = r; t < K2; ++t)
-                    acc += Mi[tri(t, r)] * Mi[tri(t, q)];
-                W[tri(r, q)] = acc;
+            for (int t = 0; t < K2; ++t) {
+                c[t] = a.cand[(size_t)i * K2 + t];
+                alive[t] = c[t] >= 0 && c[t] < n;
+                if (!alive[t])
+                    c[t] = 0;
+                b[t] = alive[t] ? sBX[tid * kPruneSlots + t] : 0.f;
             }
+            float Gc[NT];
 #pragma unroll
-        for (int r = 0; r < K2; ++r) {
-            float acc = 0.f;
+            for (int r = 0; r < K2; ++r)
 #pragma unroll
-            for (int q = 0; q < K2; ++q)
-                acc += W[r >= q ? tri(r, q) : tri(q, r)] * b[q];
-            x[r] = acc;
-        }
-        while (kept > s) {
-            // the removal that raises the residual least
-            float best = INFINITY;
-            int batom = 0x7fffffff;
-            bool oh[K2];
+                for (int qq = 0; qq <= r; ++qq)
+                    Gc[tri(r, qq)] = a.G[(size_t)c[r] * ldn + c[qq]];
+            int kept = 0;
 #pragma unroll
-            for (int j = 0; j < K2; ++j) {
-                const float cost = x[j] * x[j] / W[tri(j, j)];
-                const bool better = alive[j] && (cost < best || (cost == best && c[j] < batom));
-                best = better ? cost : best;
-                batom = better ? c[j] : batom;
+            for (int t = 0; t < K2; ++t)
+                kept += alive[t] ? 1 : 0;
+            bool ok = true;
+            float x[K2];
+            float W[NT];
+            {
+                // W = L^{-T} L^{-1}: first M = L^{-1} (lower), then W_rq = sum_t M_tr M_tq
+                float L[NT], rd[K2];
+                masked_cholesky<K2>(Gc, alive, L, rd, ok);
+                float Mi[NT];
+#pragma unroll
+                for (int qq = 0; qq < K2; ++qq) {
+                    Mi[tri(qq, qq)] = rd[qq];
+#pragma unroll
+                    for (int r = qq + 1; r < K2; ++r) {
+                        float acc = 0.f;
+#pragma unroll
+                        for (int t = qq; t < r; ++t)
+                            acc += L[tri(r, t)] * Mi[tri(t, qq)];
+                        Mi[tri(r, qq)] = -acc * rd[r];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < K2; ++r)
+#pragma unroll
+                    for (int qq = 0; qq <= r; ++qq) {
+                        float acc = 0.f;
+#pragma unroll
+                        for (int t = r; t < K2; ++t)
+                            acc += Mi[tri(t, r)] * Mi[tri(t, qq)];
+                        W[tri(r, qq)] = acc;
+                    }
             }
-            float wjj = 1.f, xj = 0.f;
-#pragma unroll
-            for (int j = 0; j < K2; ++j) {
-                oh[j] = alive[j] && c[j] == batom;
-                wjj = oh[j] ? W[tri(j, j)] : wjj;
-                xj = oh[j] ? x[j] : xj;
-            }
-            // column j of W (by mask), then the rank-one downdate
-            float col[K2];
 #pragma unroll
             for (int r = 0; r < K2; ++r) {
-                float v = 0.f;
+                float acc = 0.f;
+#pragma unroll
+                for (int qq = 0; qq < K2; ++qq)
+                    acc += W[r >= qq ? tri(r, qq) : tri(qq, r)] * b[qq];
+                x[r] = acc;
+            }
+            while (kept > s) {
+                // the removal that raises the residual least
+                float best = INFINITY;
+                int batom = 0x7fffffff;
+#pragma unroll
+                for (int j = 0; j < K2; ++j) {
+                    const float cost = x[j] * x[j] * __builtin_amdgcn_rcpf(W[tri(j, j)]);
+                    const bool better =
+                        alive[j] & ((cost < best) | ((cost == best) & (c[j] < batom)));
+                    best = better ? cost : best;
+                    batom = better ? c[j] : batom;
+                }
+                bool oh[K2];
+                float wjj = 1.f, xj = 0.f;
+#pragma unroll
+                for (int j = 0; j < K2; ++j) {
+                    oh[j] = alive[j] && c[j] == batom;
+                    wjj = oh[j] ? W[tri(j, j)] : wjj;
+                    xj = oh[j] ? x[j] : xj;
+                }
+                // column j of W (by mask), then the rank-one downdate
+                float col[K2];
+#pragma unroll
+                for (int r = 0; r < K2; ++r) {
+                    float v = 0.f;
+#pragma unroll
+                    for (int j = 0; j < K2; ++j)
+                        v = oh[j] ? W[r >= j ? tri(r, j) : tri(j, r)] : v;
+                    col[r] = v;
+                }
+                const float inv = __builtin_amdgcn_rcpf(wjj);
+                const float f = xj * inv;
+#pragma unroll
+                for (int r = 0; r < K2; ++r) {
+                    x[r] -= col[r] * f;
+                    const float cr = col[r] * inv;
+#pragma unroll
+                    for (int qq = 0; qq <= r; ++qq)
+                        W[tri(r, qq)] -= cr * col[qq];
+                }
 #pragma unroll
                 for (int j = 0; j < K2; ++j)
-                    v = oh[j] ? W[r >= j ? tri(r, j) : tri(j, r)] : v;
-                col[r] = v;
+                    alive[j] = alive[j] && !oh[j];
+                --kept;
             }
-            const float inv = 1.0f / wjj;
-            const float f = xj * inv;
+            // outputs in candidate order; the survivors' (atom, coefficient)
+            // pairs also go to this signal's LDS slots for phase 3
+            float *mine = sBX + tid * kPruneSlots;
+            int slot = 0;
 #pragma unroll
-            for (int r = 0; r < K2; ++r) {
-                x[r] -= col[r] * f;
-                const float cr = col[r] * inv;
-#pragma unroll
-                for (int q = 0; q <= r; ++q)
-                    W[tri(r, q)] -= cr * col[q];
+            for (int t = 0; t < K2; ++t)
+                if (alive[t] && slot < s) {
+                    a.idx[(size_t)i * s + slot] = c[t];
+                    a.val[(size_t)i * s + slot] = x[t];
+                    mine[2 * slot] = __int_as_float(c[t]);
+                    mine[2 * slot + 1] = x[t];
+                    ++slot;
+                }
+            for (int t = slot; t < s; ++t) {
+                a.idx[(size_t)i * s + t] = -1;
+                a.val[(size_t)i * s + t] = 0.f;
+                mine[2 * t] = __int_as_float(0);
+                mine[2 * t + 1] = 0.f;
             }
-#pragma unroll
-            for (int j = 0; j < K2; ++j)
-                alive[j] = alive[j] && !oh[j];
-            --kept;
+            sOk[tid] = ok ? 1 : 0;
         }
-    }
-    {
-        // least squares on the survivors: a fresh masked Cholesky solve
-        float L[NT], rd[K2];
-        masked_cholesky<K2>(Gc, alive, L, rd, ok);
-        float z[K2];
-#pragma unroll
-        for (int r = 0; r < K2; ++r) {
-            float acc = alive[r] ? b[r] : 0.f;
-#pragma unroll
-            for (int t = 0; t < r; ++t)
-                acc -= L[tri(r, t)] * z[t];
-            z[r] = acc * rd[r];
-        }
-#pragma unroll
-        for (int r = K2 - 1; r >= 0; --r) {
-            float acc = z[r];
-#pragma unroll
-            for (int t = r + 1; t < K2; ++t)
-                acc -= L[tri(t, r)] * x[t];
-            x[r] = acc * rd[r];
-        }
-    }
+        __syncthreads();
 
-    // explicit residual and the fallback test
-    float enorm2 = 0.f;
-    for (int q = 0; q < p; q += 4) {
-        f32x4 e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
-#pragma unroll
-        for (int t = 0; t < K2; ++t)
-            if (alive[t])
-                e -= *reinterpret_cast<const f32x4 *>(a.D + (size_t)c[t] * p + q) * x[t];
-        if (valid)
-            *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e;
-        enorm2 += e[0] * e[0] + e[1] * e[1] + e[2] * e[2] + e[3] * e[3];
-    }
-    if (valid) {
-        int slot = 0;
-#pragma unroll
-        for (int t = 0; t < K2; ++t)
-            if (alive[t] && slot < s) {
-                a.idx[(size_t)i * s + slot] = c[t];
-                a.val[(size_t)i * s + slot] = x[t];
-                ++slot;
+        // ---- phase 3: residual rows and the fallback test
+        for (int il0 = wave * GPW; il0 < kPruneBlock; il0 += NW * GPW) {
+            const int il = il0 + g;
+            const bool on = il < nsig;
+            const int i = i0 + (on ? il : 0);
+            f32x4 e = zero;
+            if (on && q < p)
+                e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
+            const float *mine = sBX + (on ? il : 0) * kPruneSlots;
+            for (int t = 0; t < s; ++t) {
+                const int c = on ? __float_as_int(mine[2 * t]) : 0;
+                const float xv = on ? mine[2 * t + 1] : 0.f;
+                if (q < p)
+                    e -= *reinterpret_cast<const f32x4 *>(Dr + (size_t)c * p + q) * xv;
             }
-        for (int t = slot; t < s; ++t) {
-            a.idx[(size_t)i * s + t] = -1;
-            a.val[(size_t)i * s + t] = 0.f;
+            if (on && q < p)
+                *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e;
+            const float enorm = sqrtf(lane_group_sum<LPU>(e[0] * e[0] + e[1] * e[1] +
+                                                          e[2] * e[2] + e[3] * e[3]));
+            if (on && l == 0 && (!sOk[il] || !(enorm <= (1.f + a.margin) * a.rref[i])))
+                sFb[atomicAdd(&sFbCount, 1)] = i;
         }
+        __syncthreads();
+        const int cnt = sFbCount;
+        if (tid == 0 && cnt > 0) {
+            sFbBase = atomicAdd(a.fb_count, cnt);
+            atomicAdd(&a.ctl->fallbacks, (unsigned long long)cnt);
+        }
+        __syncthreads();
+        for (int k = tid; k < cnt; k += kPruneBlock)
+            a.fb_list[sFbBase + k] = sFb[k];
     }
-    // The rejected signals of the wave take consecutive places of the
-    // fallback list: one atomic per wave (a per-signal atomic on the one
-    // counter serialises most of the launch when most signals fall back).
-    // The list order only decides where OMP codes a signal, not its result.
-    const float enorm = sqrtf(enorm2);
-    const bool fb = valid && (!ok || !(enorm <= (1.f + a.margin) * a.rref[i]));
-    const unsigned long long mask = __ballot(fb);
-    const int lane = threadIdx.x & 63;
-    const int cnt = __popcll(mask);
-    int base = 0;
-    if (lane == 0 && cnt > 0) {
-        base = atomicAdd(a.fb_count, cnt);
-        atomicAdd(&a.ctl->fallbacks, (unsigned long long)cnt);
-    }
-    base = __shfl(base, 0);
-    if (fb)
-        a.fb_list[base + __popcll(mask & ((1ull << lane) - 1ull))] = i;
 }
 
 // rows[k] = src[list[k]] for k < *count (p floats per row)
@@ -367,22 +429,53 @@ __global__ void gather_list_kernel(const float *__restrict__ src, int p,
 
 }  // namespace
 
+template <int K2, bool DLDS>
+hipError_t launch_ls_prune_k(const ProposeArgs &a, hipStream_t st)
+{
+    int lpu = 1;
+    while (4 * lpu < a.p)
+        lpu <<= 1;
+    const int blocks = (a.m + kPruneBlock - 1) / kPruneBlock;
+    const void *kern;
+    switch (lpu) {
+    case 1:
+    case 2:
+    case 4: kern = (const void *)ls_prune_kernel<K2, 4, DLDS>; break;
+    case 8: kern = (const void *)ls_prune_kernel<K2, 8, DLDS>; break;
+    case 16: kern = (const void *)ls_prune_kernel<K2, 16, DLDS>; break;
+    case 32: kern = (const void *)ls_prune_kernel<K2, 32, DLDS>; break;
+    default: kern = (const void *)ls_prune_kernel<K2, 64, DLDS>; break;
+    }
+    // persistent workgroups: each stages the dictionary once and then codes
+    // block after block
+    const dim3 grid(batch_workers(kern, kPruneBlock, 0, blocks));
+    switch (lpu) {
+    case 1:
+    case 2:
+    case 4: hipLaunchKernelGGL((ls_prune_kernel<K2, 4, DLDS>), grid, dim3(kPruneBlock), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((ls_prune_kernel<K2, 8, DLDS>), grid, dim3(kPruneBlock), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((ls_prune_kernel<K2, 16, DLDS>), grid, dim3(kPruneBlock), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((ls_prune_kernel<K2, 32, DLDS>), grid, dim3(kPruneBlock), 0, st, a); break;
+    default: hipLaunchKernelGGL((ls_prune_kernel<K2, 64, DLDS>), grid, dim3(kPruneBlock), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_ls_prune(const ProposeArgs &a, int k2, hipStream_t st)
 {
-    const dim3 grid((a.m + 255) / 256);
-    prof_begin(DL_K_PROPOSE, st);
-    if (k2 == 8)
-        hipLaunchKernelGGL(ls_prune_kernel<8>, grid, dim3(256), 0, st, a);
-    else if (k2 == 12)
-        hipLaunchKernelGGL(ls_prune_kernel<12>, grid, dim3(256), 0, st, a);
-    else if (k2 == 16)
-        hipLaunchKernelGGL(ls_prune_kernel<16>, grid, dim3(256), 0, st, a);
-    else {
-        prof_end(DL_K_PROPOSE, st);
+    if ((k2 != 8 && k2 != 12 && k2 != 16) || a.s > k2 || a.p > 256 || a.p % 4 != 0)
         return hipErrorInvalidValue;
-    }
+    const bool in_lds = (long long)a.n * a.p <= kPruneLdsFloats;
+    prof_begin(DL_K_PROPOSE, st);
+    hipError_t e;
+    if (k2 == 8)
+        e = in_lds ? launch_ls_prune_k<8, true>(a, st) : launch_ls_prune_k<8, false>(a, st);
+    else if (k2 == 12)
+        e = in_lds ? launch_ls_prune_k<12, true>(a, st) : launch_ls_prune_k<12, false>(a, st);
+    else
+        e = in_lds ? launch_ls_prune_k<16, true>(a, st) : launch_ls_prune_k<16, false>(a, st);
     prof_end(DL_K_PROPOSE, st);
-    return hipGetLastError();
+    return e;
 }
 
 hipError_t launch_gather_list(const float *src, int p, const int32_t *list, const int32_t *count,
