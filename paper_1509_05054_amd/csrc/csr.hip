@@ -278,18 +278,18 @@ __global__ __launch_bounds__(256) void csr_scatter_kernel(
 __device__ inline int csr_nb(int m) { return (m + kCsrBlock - 1) / kCsrBlock; }
 
 __global__ __launch_bounds__(kCsrBlock) void csr_count_batched(const CsrArgs *__restrict__ tab,
-                                                               BatchList bl)
+                                                               BatchList bl, int per)
 {
     extern __shared__ unsigned long long smem[];
     __shared__ int slot;
     const int total = bl.start[bl.count];
-    for (;;) {
-        const int it = batch_next_item(bl.q, &slot);
-        if (it >= total)
-            break;
-        const int b = batch_find(bl.start, bl.count, it);
-        const CsrArgs a = tab[b];
-        csr_count_body(a.idx, a.blkcnt, a.lrank, a.n, a.m, a.s, csr_nb(a.m), it - bl.start[b],
+    BatchCursor cur;
+    BatchOwner own;
+    CsrArgs a;
+    while (batch_advance(bl.q, total, per, cur, &slot)) {
+        if (batch_owner(bl.start, bl.count, cur.it, own))
+            a = tab[own.b];
+        csr_count_body(a.idx, a.blkcnt, a.lrank, a.n, a.m, a.s, csr_nb(a.m), cur.it - own.b0,
                        smem);
     }
     if (threadIdx.x == 0)
@@ -301,43 +301,44 @@ __global__ __launch_bounds__(kCsrBlock) void csr_count_batched(const CsrArgs *__
 __global__ __launch_bounds__(256) void csr_scan_batched(const CsrArgs *__restrict__ tab,
                                                         BatchList bl,
                                                         const RmseArgs *__restrict__ etab,
-                                                        BatchList el, int k)
+                                                        BatchList el, int k, int per)
 {
     __shared__ int slot;
     const int scans = bl.start[bl.count];
     const int total = scans + (etab ? el.start[el.count] : 0);
-    for (;;) {
-        const int it = batch_next_item(bl.q, &slot);
-        if (it >= total)
-            break;
+    BatchCursor cur;
+    BatchOwner own;
+    CsrArgs a;
+    while (batch_advance(bl.q, total, per, cur, &slot)) {
+        const int it = cur.it;
         if (it >= scans) {
-            RmseArgs a = etab[batch_find(el.start, el.count, it - scans)];
-            a.out += k;
-            rmse_final_body(a, rmse_blocks_dev(a.m));
+            RmseArgs e = etab[batch_find(el.start, el.count, it - scans)];
+            e.out += k;
+            rmse_final_body(e, rmse_blocks_dev(e.m));
             continue;
         }
-        const int b = batch_find(bl.start, bl.count, it);
-        const CsrArgs a = tab[b];
-        csr_scan_body(a.blkcnt, a.tot, a.n, csr_nb(a.m), it - bl.start[b]);
+        if (batch_owner(bl.start, bl.count, it, own))
+            a = tab[own.b];
+        csr_scan_body(a.blkcnt, a.tot, a.n, csr_nb(a.m), it - own.b0);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void csr_scatter_batched(const CsrArgs *__restrict__ tab,
-                                                           BatchList bl)
+                                                           BatchList bl, int per)
 {
     __shared__ int slot;
     const int total = bl.start[bl.count];
-    for (;;) {
-        const int it = batch_next_item(bl.q, &slot);
-        if (it >= total)
-            break;
-        const int b = batch_find(bl.start, bl.count, it);
-        const CsrArgs a = tab[b];
+    BatchCursor cur;
+    BatchOwner own;
+    CsrArgs a;
+    while (batch_advance(bl.q, total, per, cur, &slot)) {
+        if (batch_owner(bl.start, bl.count, cur.it, own))
+            a = tab[own.b];
         csr_scatter_body(a.idx, a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.lrank, a.users,
-                         a.uent, a.val, a.val_pad, a.n, a.m, a.s, csr_nb(a.m), it - bl.start[b],
-                         bl.start[b + 1] - bl.start[b]);
+                         a.uent, a.val, a.val_pad, a.n, a.m, a.s, csr_nb(a.m), cur.it - own.b0,
+                         own.b1 - own.b0);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -356,7 +357,8 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
     const size_t shmem = (sizeof(unsigned long long) + sizeof(int32_t)) * kWavesPerBlock * max_n;
     int wg = batch_workers((const void *)csr_count_batched, kCsrBlock, shmem, count_items);
     prof_begin(DL_K_CSR_COUNT, st);
-    hipLaunchKernelGGL(csr_count_batched, dim3(wg), dim3(kCsrBlock), shmem, st, tab, count_list);
+    hipLaunchKernelGGL(csr_count_batched, dim3(wg), dim3(kCsrBlock), shmem, st, tab, count_list,
+                       batch_per_ticket(count_items, wg));
     prof_end(DL_K_CSR_COUNT, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -365,13 +367,14 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
                        scan_items + (etab ? el.count : 0));
     prof_begin(DL_K_CSR_SCAN, st);
     hipLaunchKernelGGL(csr_scan_batched, dim3(wg), dim3(256), 0, st, tab, scan_list, etab, el,
-                       k);
+                       k, batch_per_ticket(scan_items + (etab ? el.count : 0), wg));
     prof_end(DL_K_CSR_SCAN, st);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     wg = batch_workers((const void *)csr_scatter_batched, 256, 0, scatter_items);
     prof_begin(DL_K_CSR_SCATTER, st);
-    hipLaunchKernelGGL(csr_scatter_batched, dim3(wg), dim3(256), 0, st, tab, scatter_list);
+    hipLaunchKernelGGL(csr_scatter_batched, dim3(wg), dim3(256), 0, st, tab, scatter_list,
+                       batch_per_ticket(scatter_items, wg));
     prof_end(DL_K_CSR_SCATTER, st);
     return hipGetLastError();
 }

@@ -286,6 +286,54 @@ __device__ inline int batch_next_item(BatchQueue *q, int *slot)
     return __builtin_amdgcn_readfirstlane(*slot);
 }
 
+// Workgroup-wide cursor over a batched launch's items: a ticket is `per`
+// consecutive items, so the one counter sees a few atomics per workgroup
+// rather than one per item.  Every call begins with a workgroup barrier (the
+// previous item's shared memory is no longer read); it returns false when
+// no item is left.
+struct BatchCursor {
+    int it = 0, end = 0;
+};
+__device__ inline bool batch_advance(BatchQueue *q, int total, int per, BatchCursor &c, int *slot)
+{
+    if (c.it + 1 < c.end) {
+        __syncthreads();
+        ++c.it;
+        return true;
+    }
+    const int tk = batch_next_item(q, slot);
+    const long long first = (long long)tk * per;
+    if (first >= total)
+        return false;
+    c.it = (int)first;
+    c.end = (int)(first + per < total ? first + per : total);
+    return true;
+}
+
+// The problem owning item `it` of a list, looked up again only when `it`
+// leaves the cached problem's item range [b0, b1).  Returns true when the
+// problem changed (its arguments must be reloaded).
+struct BatchOwner {
+    int b = -1, b0 = 0, b1 = 0;
+};
+__device__ inline bool batch_owner(const int32_t *start, int count, int it, BatchOwner &o)
+{
+    if (o.b >= 0 && it >= o.b0 && it < o.b1)
+        return false;
+    o.b = batch_find(start, count, it);
+    o.b0 = start[o.b];
+    o.b1 = start[o.b + 1];
+    return true;
+}
+
+// Items per ticket for a launch of `workers` workgroups: about eight tickets
+// per workgroup, at most 16 items each.
+inline int batch_per_ticket(int items, int workers)
+{
+    long long per = (long long)items / (8ll * (workers > 0 ? workers : 1));
+    return per < 1 ? 1 : (per > 16 ? 16 : (int)per);
+}
+
 // Called once by every worker after its last item; `workers` is the number
 // of workers in the launch.  Only the counters are shared (results reach the
 // next launch through the launch boundary), so no fence is needed.

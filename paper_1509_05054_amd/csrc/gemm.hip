@@ -236,25 +236,32 @@ __host__ __device__ inline int gemm_tiles(const GemmF32 &P)
 __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmPair *__restrict__ tab,
                                                            BatchList bl,
                                                            const RmseArgs *__restrict__ etab,
-                                                           BatchList el)
+                                                           BatchList el, int per)
 {
     __shared__ int slot;
     const int tiles = bl.start[bl.count];
     const int total = tiles + (etab ? el.start[el.count] : 0);
-    for (;;) {
-        const int it = batch_next_item(bl.q, &slot);
-        if (it >= total)
-            break;
+    BatchCursor cur;
+    BatchOwner own, eown;
+    GemmF32 G, C;
+    int tg = 0;
+    RmseArgs ea;
+    while (batch_advance(bl.q, total, per, cur, &slot)) {
+        const int it = cur.it;
         if (it >= tiles) {
             const int e = it - tiles;
-            const int b = batch_find(el.start, el.count, e);
-            rmse_body(etab[b], e - el.start[b], el.start[b + 1] - el.start[b]);
+            if (batch_owner(el.start, el.count, e, eown))
+                ea = etab[eown.b];
+            rmse_body(ea, e - eown.b0, eown.b1 - eown.b0);
             continue;
         }
-        const int b = batch_find(bl.start, bl.count, it);
-        int t = it - bl.start[b];
-        const int tg = gemm_tiles(tab[b].g);
-        const GemmF32 P = t < tg ? tab[b].g : tab[b].c;
+        if (batch_owner(bl.start, bl.count, it, own)) {
+            G = tab[own.b].g;
+            C = tab[own.b].c;
+            tg = gemm_tiles(G);
+        }
+        int t = it - own.b0;
+        const GemmF32 &P = t < tg ? G : C;
         if (t >= tg)
             t -= tg;
         const int tx = (P.N + kBlockN - 1) / kBlockN;
@@ -432,7 +439,8 @@ hipError_t launch_batched_gemm(const GemmPair *tab, const BatchList &bl, int ite
     const int wg = batch_workers((const void *)gemm_batched_kernel, 256, 0,
                                  items + (etab ? eitems : 0));
     prof_begin(DL_K_CORR, st);
-    hipLaunchKernelGGL(gemm_batched_kernel, dim3(wg), dim3(256), 0, st, tab, bl, etab, el);
+    hipLaunchKernelGGL(gemm_batched_kernel, dim3(wg), dim3(256), 0, st, tab, bl, etab, el,
+                       batch_per_ticket(items + (etab ? eitems : 0), wg));
     prof_end(DL_K_CORR, st);
     return hipGetLastError();
 }

@@ -395,17 +395,17 @@ __global__ __launch_bounds__(256) void normalize_kernel(float *D, int n, int p, 
 // normalisation = atom quads.
 template <int STAGE>
 __global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restrict__ tab,
-                                                      BatchList bl)
+                                                      BatchList bl, int per)
 {
     __shared__ int slot;
     const int total = bl.start[bl.count];
-    for (;;) {
-        const int it = batch_next_item(bl.q, &slot);
-        if (it >= total)
-            break;
-        const int b = batch_find(bl.start, bl.count, it);
-        const UpdateArgs a = tab[b];
-        const int t = it - bl.start[b], nt = bl.start[b + 1] - bl.start[b];
+    BatchCursor cur;
+    BatchOwner own;
+    UpdateArgs a;
+    while (batch_advance(bl.q, total, per, cur, &slot)) {
+        if (batch_owner(bl.start, bl.count, cur.it, own))
+            a = tab[own.b];
+        const int t = cur.it - own.b0, nt = own.b1 - own.b0;
         if (STAGE == 0)
             pass1_body(a, 0, a.n, t, nt);
         else
@@ -417,16 +417,18 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restri
 
 // Block partials of every problem; the error of iteration k then goes to
 // out[k] of every problem (rmse_final_batched).
-__global__ __launch_bounds__(256) void rmse_batched(const RmseArgs *__restrict__ tab, BatchList bl)
+__global__ __launch_bounds__(256) void rmse_batched(const RmseArgs *__restrict__ tab, BatchList bl,
+                                                    int per)
 {
     __shared__ int slot;
     const int total = bl.start[bl.count];
-    for (;;) {
-        const int it = batch_next_item(bl.q, &slot);
-        if (it >= total)
-            break;
-        const int b = batch_find(bl.start, bl.count, it);
-        rmse_body(tab[b], it - bl.start[b], bl.start[b + 1] - bl.start[b]);
+    BatchCursor cur;
+    BatchOwner own;
+    RmseArgs a;
+    while (batch_advance(bl.q, total, per, cur, &slot)) {
+        if (batch_owner(bl.start, bl.count, cur.it, own))
+            a = tab[own.b];
+        rmse_body(a, cur.it - own.b0, own.b1 - own.b0);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -452,17 +454,17 @@ __global__ __launch_bounds__(256) void rmse_final_batched(const RmseArgs *__rest
 }
 
 __global__ __launch_bounds__(256) void normalize_batched(const NormArgs *__restrict__ tab,
-                                                         BatchList bl)
+                                                         BatchList bl, int per)
 {
     __shared__ int slot;
     const int total = bl.start[bl.count];
-    for (;;) {
-        const int it = batch_next_item(bl.q, &slot);
-        if (it >= total)
-            break;
-        const int b = batch_find(bl.start, bl.count, it);
-        const NormArgs a = tab[b];
-        normalize_body(a.D, a.n, a.p, a.ctl, it - bl.start[b]);
+    BatchCursor cur;
+    BatchOwner own;
+    NormArgs a;
+    while (batch_advance(bl.q, total, per, cur, &slot)) {
+        if (batch_owner(bl.start, bl.count, cur.it, own))
+            a = tab[own.b];
+        normalize_body(a.D, a.n, a.p, a.ctl, cur.it - own.b0);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -553,14 +555,16 @@ hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_l
 {
     int wg = batch_workers((const void *)update_batched<0>, 256, 0, chunk_items);
     prof_begin(DL_K_UPD_PASS1, st);
-    hipLaunchKernelGGL(update_batched<0>, dim3(wg), dim3(256), 0, st, tab, chunk_list);
+    hipLaunchKernelGGL(update_batched<0>, dim3(wg), dim3(256), 0, st, tab, chunk_list,
+                       batch_per_ticket(chunk_items, wg));
     prof_end(DL_K_UPD_PASS1, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     wg = batch_workers((const void *)update_batched<2>, 256, 0, chunk_items);
     prof_begin(DL_K_UPD_PASS2, st);
-    hipLaunchKernelGGL(update_batched<2>, dim3(wg), dim3(256), 0, st, tab, chunk_list);
+    hipLaunchKernelGGL(update_batched<2>, dim3(wg), dim3(256), 0, st, tab, chunk_list,
+                       batch_per_ticket(chunk_items, wg));
     prof_end(DL_K_UPD_PASS2, st);
     return hipGetLastError();
 }
@@ -570,7 +574,8 @@ hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int ite
 {
     int wg = batch_workers((const void *)rmse_batched, 256, 0, items);
     prof_begin(DL_K_RMSE, st);
-    hipLaunchKernelGGL(rmse_batched, dim3(wg), dim3(256), 0, st, tab, bl);
+    hipLaunchKernelGGL(rmse_batched, dim3(wg), dim3(256), 0, st, tab, bl,
+                       batch_per_ticket(items, wg));
     prof_end(DL_K_RMSE, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -587,7 +592,8 @@ hipError_t launch_batched_normalize(const NormArgs *tab, const BatchList &bl, in
 {
     const int wg = batch_workers((const void *)normalize_batched, 256, 0, items);
     prof_begin(DL_K_MISC, st);
-    hipLaunchKernelGGL(normalize_batched, dim3(wg), dim3(256), 0, st, tab, bl);
+    hipLaunchKernelGGL(normalize_batched, dim3(wg), dim3(256), 0, st, tab, bl,
+                       batch_per_ticket(items, wg));
     prof_end(DL_K_MISC, st);
     return hipGetLastError();
 }
