@@ -10,6 +10,8 @@ namespace dlk {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+bool error_carried(const dl_params &prm) { return prm.group_size >= prm.n && error_defer_ok(prm.m); }
+
 Layout layout_for(const dl_params &prm)
 {
     const size_t p = prm.p, n = prm.n, m = prm.m, s = prm.s;
@@ -38,12 +40,13 @@ Layout layout_for(const dl_params &prm)
     L.atom_state = take(sizeof(int32_t) * n);
     L.partial = take(sizeof(float) * (size_t)max_chunks(prm) * p);
     L.rmse_part = take(sizeof(double) * (size_t)rmse_blocks(prm.m));
-    if (prm.rule == DL_RULE_NSGK) {
+    if (prm.rule == DL_RULE_NSGK || error_carried(prm)) {
         L.idx_prev = take(sizeof(int32_t) * m * s);
         L.val_prev = take(sizeof(float) * m * s);
     } else {
         L.idx_prev = L.val_prev = 0;
     }
+    L.E2 = error_carried(prm) ? take(sizeof(float) * m * p) : 0;
     if (prm.precision == DL_PREC_BF16) {
         L.Dbf = take(sizeof(uint16_t) * n * p);
         L.Ybf = take(sizeof(uint16_t) * m * p);
@@ -168,8 +171,12 @@ struct OmpExtra {
     const int32_t *m_dev = nullptr;
     const int32_t *rowmap = nullptr;
     float *rnorm = nullptr;
+    float *E = nullptr;            // residual rows (default: the workspace's E)
     bool products = true;          // form G and A0 here
-    const RmseArgs *prev_err = nullptr;  // error partials carried by the products launch
+    // error partials carried by the coding launch (one wave per signal
+    // group), else by the products launch; the coding must not write what
+    // the error reads (X, E)
+    const RmseArgs *prev_err = nullptr;
 };
 
 dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t *idx, float *val,
@@ -178,9 +185,12 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
     float *G = ws.at<float>(ws.L.G);
     float *A0 = ws.at<float>(ws.L.A0);
     const float *Yin = x.Y ? x.Y : Y;
+    const bool err_in_coding =
+        x.prev_err && omp_carries_error(prm.n, prm.s, prm.omp_lanes_per_signal,
+                                        prm.omp_atoms_per_lane);
     if (x.products) {
         dl_status rc = products(prm, D, Yin, G, A0, &ws, st, padded_n(prm.n), nullptr,
-                                x.prev_err);
+                                err_in_coding ? nullptr : x.prev_err);
         if (rc != DL_OK)
             return rc;
     }
@@ -193,7 +203,7 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
     a.D = D;
     a.idx = idx;
     a.val = val;
-    a.E = ws.at<float>(ws.L.E);
+    a.E = x.E ? x.E : ws.at<float>(ws.L.E);
     a.ctl = ws.ctl();
     a.p = prm.p;
     a.n = prm.n;
@@ -208,7 +218,7 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
     a.pivot_fp64 = prm.pivot_fp64_threshold;
     a.tol_corr = prm.tol_corr;
     a.tol_pivot = prm.tol_pivot;
-    DL_TRY(launch_omp(a, st));
+    DL_TRY(launch_omp(a, st, err_in_coding ? x.prev_err : nullptr));
     return DL_OK;
 }
 
@@ -246,7 +256,7 @@ dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, in
 dl_status run_update(const dl_params &prm, const float *Y, const float *D, float *Dn,
                      const int32_t *idx, const float *val, float *valn, const Ws &ws,
                      hipStream_t st, const RmseArgs *prev_err = nullptr,
-                     bool error_refreshes = false)
+                     bool error_refreshes = false, float *E = nullptr)
 {
     int32_t *row_ptr = ws.at<int32_t>(ws.L.row_ptr);
     int2 *uent = ws.at<int2>(ws.L.uent);
@@ -260,7 +270,7 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
     u.idx = idx;
     u.val = val;
     u.valn = valn;
-    u.E = ws.at<float>(ws.L.E);
+    u.E = E ? E : ws.at<float>(ws.L.E);
     u.row_ptr = row_ptr;
     u.chunk_ptr = ws.at<int32_t>(ws.L.chunk_ptr);
     u.uent = uent;
@@ -301,10 +311,10 @@ RmseArgs rmse_args(const dl_params &prm, const float *Y, const float *D, const i
 // coefficients val_old, the residual E and the dictionary Dold the coding
 // used (all atoms in one group, after an update with error_refreshes).
 void add_refresh(RmseArgs &r, const dl_params &prm, const float *Dold, const float *val_old,
-                 float *valn, const Ws &ws)
+                 float *valn, const Ws &ws, const float *E = nullptr)
 {
     r.Dold = Dold;
-    r.E = ws.at<float>(ws.L.E);
+    r.E = E ? E : ws.at<float>(ws.L.E);
     r.val_old = val_old;
     r.atom_state = ws.at<int32_t>(ws.L.atom_state);
     r.valn = valn;
@@ -527,36 +537,46 @@ static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, in
     // the dictionary alternates between the caller's buffer and the workspace
     float *Dcur = D, *Dnext = Dws;
     const size_t ms = (size_t)q.m * q.s;
-    // The error of iteration k needs only its outputs (Dn, X), which nothing
-    // before iteration k+1's coding overwrites.  For signal counts whose
-    // error partials take one signal block per workgroup (latency-bound
-    // sizes), its partials run as extra workgroups of k+1's products launch
-    // and its final sum in k+1's CSR scan launch: two launches fewer per
-    // iteration, with the same bodies and block decomposition as the error
-    // launches, so the same bits.  Larger counts (each partial workgroup
-    // striding over several blocks) keep the error launches, which measured
-    // faster there.  The last iteration's deferred error runs on its own.
-    // With all atoms in one group the refreshed X is read only by the error
-    // and returned: the error pass forms it (pass 2 only forms d'), reading
-    // the residual E, the coefficients and the dictionary the coding used,
-    // none of which is overwritten before iteration k+1's coding.  The
-    // carried error needs that refresh, so it is used at group size n only.
+    // The error of iteration k needs only its outputs (Dn, X), the residual
+    // E and the dictionary its coding used; nothing before iteration k+1's
+    // update overwrites them when X and E alternate between two buffers.
+    // For signal counts whose error partials take one signal block per
+    // workgroup (latency-bound sizes), its partials run as extra workgroups
+    // of k+1's coding launch (behind the coding workgroups, in its last,
+    // partly occupied round; the two-wave coding shapes carry them in the
+    // products launch instead) and its final sum in k+1's CSR scan launch:
+    // two launches fewer per iteration, with the same bodies and block
+    // decomposition as the error launches, so the same bits.  Larger counts
+    // (each partial workgroup striding over several blocks) keep the error
+    // launches, which measured faster there.  The last iteration's deferred
+    // error runs on its own.  With all atoms in one group the refreshed X is
+    // read only by the error and returned: the error pass forms it (pass 2
+    // only forms d'), reading the residual E, the coefficients and the
+    // dictionary the coding used.  The carried error needs that refresh, so
+    // it is used at group size n only.
     const bool one_group = q.group_size >= q.n;
-    const bool defer = one_group && error_defer_ok(q.m);
+    const bool defer = error_carried(q);
     // NSGK updates with the previous iteration's coding (eq. 7) and keeps X:
     // the codings alternate between the caller's X and the workspace's
     // previous-coding buffers, arranged so that the last one lands in X.
+    // A carried error runs in the next iteration's coding launch (shapes of
+    // one wave per signal group) while that coding writes its own X and E,
+    // so the codings and residuals alternate between two buffers as well.
     const bool nsgk = q.rule == DL_RULE_NSGK;
-    int32_t *idx_buf[2] = {X_idx, nsgk ? w.at<int32_t>(w.L.idx_prev) : nullptr};
-    float *val_buf[2] = {X_val, nsgk ? w.at<float>(w.L.val_prev) : nullptr};
+    const bool alt = nsgk || defer;
+    int32_t *idx_buf[2] = {X_idx, alt ? w.at<int32_t>(w.L.idx_prev) : nullptr};
+    float *val_buf[2] = {nsgk ? X_val : val_ws, alt ? w.at<float>(w.L.val_prev) : nullptr};
+    float *E_buf[2] = {w.at<float>(w.L.E), defer ? w.at<float>(w.L.E2) : nullptr};
     RmseArgs prev{};
     bool pending = false;
     for (int k = 0; k < iters; ++k) {
         const int cb = (iters - 1 - k) & 1;
-        int32_t *idx_k = nsgk ? idx_buf[cb] : X_idx;
-        float *val_k = nsgk ? val_buf[cb] : val_ws;
+        int32_t *idx_k = alt ? idx_buf[cb] : X_idx;
+        float *val_k = alt ? val_buf[cb] : val_ws;
+        float *E_k = defer ? E_buf[cb] : E_buf[0];
         OmpExtra x;
         x.rnorm = rref;
+        x.E = E_k;
         x.prev_err = pending ? &prev : nullptr;
         rc = run_omp(q, Dcur, Y, idx_k, val_k, w, st, x);
         if (rc != DL_OK)
@@ -569,17 +589,17 @@ static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, in
             const int32_t *idx_p = k == 0 ? idx_k : idx_buf[cb ^ 1];
             const float *val_p = k == 0 ? val_k : val_buf[cb ^ 1];
             rc = run_update(q, Y, Dcur, Dnext, idx_p, val_p, w.at<float>(w.L.valn), w, st,
-                            pending ? &prev : nullptr, one_group);
+                            pending ? &prev : nullptr, one_group, E_k);
         } else {
             rc = run_update(q, Y, Dcur, Dnext, idx_k, val_k, X_val, w, st,
-                            pending ? &prev : nullptr, one_group);
+                            pending ? &prev : nullptr, one_group, E_k);
         }
         if (rc != DL_OK)
             return rc;
         float *xout = nsgk ? val_k : X_val;
         prev = rmse_args(q, Y, Dnext, idx_k, xout, rmse + k, w);
         if (one_group)
-            add_refresh(prev, q, Dcur, val_k, xout, w);
+            add_refresh(prev, q, Dcur, val_k, xout, w, E_k);
         pending = defer;
         if (!defer)
             DL_TRY(launch_rmse(prev, st));

@@ -50,8 +50,9 @@ struct Layout {
     size_t atom_state; // [n] int: 0 updated, 1 no users, 2 zero F x^T
     size_t partial;    // [max_chunks][p] float
     size_t rmse_part;  // [rmse_blocks(m)] double
-    size_t idx_prev;   // [m][s] int, previous coding (NSGK rule only)
-    size_t val_prev;   // [m][s] float, previous coding (NSGK rule only)
+    size_t idx_prev;   // [m][s] int, previous coding (NSGK rule, or a carried error)
+    size_t val_prev;   // [m][s] float, previous coding (NSGK rule, or a carried error)
+    size_t E2;         // [m][p] float, the previous iteration's residual (carried error only)
     size_t Dbf;        // [n][p] bf16 (precision variant)
     size_t Ybf;        // [m][p] bf16 (precision variant)
     size_t total;
@@ -110,7 +111,11 @@ struct OmpArgs {
     int atoms_per_lane;    // 8 or 16, or 0 for the default (16)
     float pivot_fp64, tol_corr, tol_pivot;
 };
-hipError_t launch_omp(const OmpArgs &a, hipStream_t st);
+// err: optional error partials (rmse_blocks(err->m) workgroups of the
+// refreshing error pass) run by extra workgroups behind the coding ones;
+// only shapes of one wave per signal group take them (omp_carries_error).
+hipError_t launch_omp(const OmpArgs &a, hipStream_t st, const RmseArgs *err = nullptr);
+bool omp_carries_error(int n, int s, int lps_req, int npl_req);
 int omp_lanes_per_signal(int n, int npl, int s);
 bool omp_config_ok(int n, int s, int lps, int npl);
 // Leading dimension used for G and A0 rows.
@@ -180,6 +185,10 @@ constexpr int kRmseMaxPartials = 1024;
 // Whether an error over m signals is one signal block per partial workgroup
 // (the sizes at which it is carried by the next iteration's launches).
 bool error_defer_ok(int m);
+// Whether dl_iterate carries each iteration's error into the next one's
+// launches (all atoms in one group, error_defer_ok); the coding then keeps
+// two sets of X and E buffers, alternating between iterations.
+bool error_carried(const dl_params &prm);
 
 // E = Y - D X (one signal per lane group).
 hipError_t launch_residual(const float *Y, const float *D, const int32_t *idx, const float *val,

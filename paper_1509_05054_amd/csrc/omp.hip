@@ -67,19 +67,26 @@ hipError_t launch_batched_omp(const OmpArgs *tab, const BatchList &bl, int items
     }
 }
 
-hipError_t launch_omp(const OmpArgs &a, hipStream_t st)
+bool omp_carries_error(int n, int s, int lps_req, int npl_req)
+{
+    const int npl = npl_req > 0 ? npl_req : omp_default_npl(n, s);
+    const int lps = lps_req > 0 ? lps_req : omp_lanes_per_signal(n, npl, s);
+    return omp_config_ok(n, s, lps, npl) && lps <= 64;
+}
+
+hipError_t launch_omp(const OmpArgs &a, hipStream_t st, const RmseArgs *err)
 {
     int npl = a.atoms_per_lane;
     if (npl <= 0)
         npl = omp_default_npl(a.n, a.s);
     const int lps = a.lanes_per_signal > 0 ? a.lanes_per_signal
                                            : omp_lanes_per_signal(a.n, npl, a.s);
-    if (!omp_config_ok(a.n, a.s, lps, npl))
+    if (!omp_config_ok(a.n, a.s, lps, npl) || (err && lps > 64))
         return hipErrorInvalidValue;
     switch (npl) {
-    case 4: return launch_omp_npl4(a, lps, st);
-    case 8: return launch_omp_npl8(a, lps, st);
-    default: return launch_omp_npl16(a, lps, st);
+    case 4: return launch_omp_npl4(a, lps, st, err);
+    case 8: return launch_omp_npl8(a, lps, st, err);
+    default: return launch_omp_npl16(a, lps, st, err);
     }
 }
 

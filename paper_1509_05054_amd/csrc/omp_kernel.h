@@ -27,6 +27,7 @@
 #pragma once
 
 #include "dl_internal.h"
+#include "rmse_body.h"
 
 namespace dlk {
 namespace omp_detail {
@@ -438,10 +439,18 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
 
 // Small sparsity bounds ask for three waves per SIMD (a few dwords spill;
 // measured faster than two waves without spills).
+// The err_blocks workgroups after the coding ones carry the partial pass of
+// the previous iteration's refreshing error (its X and E are not the ones
+// this coding writes); they start as coding workgroups retire, so they fill
+// the launch's last, partly occupied round.
 template <int LPS, int NPL, int SMAX>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(SMAX <= 6 ? 3 : 1)))
-void omp_kernel(OmpArgs a)
+void omp_kernel(OmpArgs a, RmseArgs err, int omp_blocks, int err_blocks)
 {
+    if ((int)blockIdx.x >= omp_blocks) {
+        rmse_refresh_body(err, (int)blockIdx.x - omp_blocks, err_blocks);
+        return;
+    }
     constexpr int GPW = 64 / LPS;
     const int m_eff = a.m_dev ? min(*a.m_dev, a.m) : a.m;
     const int wave_sig0 = (blockIdx.x * kWaves + (int)(threadIdx.x >> 6)) * GPW;
@@ -522,12 +531,14 @@ hipError_t launch_omp_batched_t(const OmpArgs *tab, const BatchList &bl, int ite
 }
 
 template <int LPS, int NPL, int SMAX>
-hipError_t launch_omp_t(const OmpArgs &a, hipStream_t st)
+hipError_t launch_omp_t(const OmpArgs &a, hipStream_t st, const RmseArgs *err)
 {
     constexpr int sig_per_block = kWaves * (64 / LPS);
     const int blocks = (a.m + sig_per_block - 1) / sig_per_block;
+    const int eb = err ? rmse_blocks_dev(err->m) : 0;
     prof_begin(DL_K_OMP, st);
-    hipLaunchKernelGGL((omp_kernel<LPS, NPL, SMAX>), dim3(blocks), dim3(64 * kWaves), 0, st, a);
+    hipLaunchKernelGGL((omp_kernel<LPS, NPL, SMAX>), dim3(blocks + eb), dim3(64 * kWaves), 0, st,
+                       a, err ? *err : RmseArgs{}, blocks, eb);
     prof_end(DL_K_OMP, st);
     return hipGetLastError();
 }
@@ -576,29 +587,29 @@ hipError_t launch_omp_batched_s(const OmpArgs *tab, const BatchList &bl, int ite
 // Dispatch over SMAX for one (LPS, NPL); configurations with LPS < SMAX are
 // never requested (omp_config_ok rejects them).
 template <int LPS, int NPL>
-hipError_t launch_omp_s(const OmpArgs &a, hipStream_t st)
+hipError_t launch_omp_s(const OmpArgs &a, hipStream_t st, const RmseArgs *err)
 {
     if (a.s <= 4)
-        return launch_omp_t<LPS, NPL, 4>(a, st);
+        return launch_omp_t<LPS, NPL, 4>(a, st, err);
     if constexpr (LPS >= 8) {
         if (a.s <= 6)
-            return launch_omp_t<LPS, NPL, 6>(a, st);
+            return launch_omp_t<LPS, NPL, 6>(a, st, err);
         if (a.s <= 8)
-            return launch_omp_t<LPS, NPL, 8>(a, st);
+            return launch_omp_t<LPS, NPL, 8>(a, st, err);
     }
     if constexpr (LPS >= 16) {
         if (a.s <= 12)
-            return launch_omp_t<LPS, NPL, 12>(a, st);
-        return launch_omp_t<LPS, NPL, 16>(a, st);
+            return launch_omp_t<LPS, NPL, 12>(a, st, err);
+        return launch_omp_t<LPS, NPL, 16>(a, st, err);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace omp_detail
 
-hipError_t launch_omp_npl4(const OmpArgs &a, int lps, hipStream_t st);
-hipError_t launch_omp_npl8(const OmpArgs &a, int lps, hipStream_t st);
-hipError_t launch_omp_npl16(const OmpArgs &a, int lps, hipStream_t st);
+hipError_t launch_omp_npl4(const OmpArgs &a, int lps, hipStream_t st, const RmseArgs *err);
+hipError_t launch_omp_npl8(const OmpArgs &a, int lps, hipStream_t st, const RmseArgs *err);
+hipError_t launch_omp_npl16(const OmpArgs &a, int lps, hipStream_t st, const RmseArgs *err);
 hipError_t launch_omp_batched_npl4(const OmpArgs *tab, const BatchList &bl, int items, int lps,
                                    int smax, hipStream_t st);
 hipError_t launch_omp_batched_npl8(const OmpArgs *tab, const BatchList &bl, int items, int lps,
