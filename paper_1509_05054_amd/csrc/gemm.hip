@@ -203,10 +203,10 @@ __device__ inline void gemm_f32_tile(const GemmF32 &P, int brow0, int bcol0)
     store_block<TM, BM>(P.C, M, N, P.ldc, brow0, bcol0, acc, lds);
 }
 
-// Workgroup tiles of 128 rows (TM = 4) for single-problem and batched
-// products alike (measured: faster than 64-row tiles that load their
-// operands straight into the MFMA layout, at m = 16384 and 262144 and for
-// the batched problems).
+// Workgroup tiles of 128 rows (TM = 4) for the batched products and the
+// large single-problem ones (measured: faster than 64-row tiles that load
+// their operands straight into the MFMA layout, at m = 262144 and for the
+// batched problems); small single problems take 32-row tiles (below).
 constexpr int kF32TM = 4;
 constexpr int kF32M = 32 * kF32TM;
 
@@ -421,6 +421,14 @@ hipError_t launch_grouped(Kern kern, const P &p0, const P *p1, int kid, hipStrea
 hipError_t launch_gemm_nt_f32(const GemmF32 &p0, const GemmF32 *p1, int kid, hipStream_t st,
                               const RmseArgs *err)
 {
+    // 32-row tiles while 128-row tiles would give fewer than four per CU
+    // (measured at p = 64, n = 256: m = 16384 products 17.1 -> 14.9 us; at
+    // m = 262144 the 128-row tiles stay faster, 123 vs 143 us); every element
+    // is summed in the same order either way
+    const long long rows = (long long)p0.M + (p1 ? p1->M : 0);
+    const long long tiles128 = ((rows + 127) / 128) * ((p0.N + kBlockN - 1) / kBlockN);
+    if (tiles128 < 1024)
+        return launch_grouped(gemm_nt_f32_kernel<1>, p0, p1, kid, st, 32, err);
     return launch_grouped(gemm_nt_f32_kernel<4>, p0, p1, kid, st, 128, err);
 }
 
