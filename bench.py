@@ -626,6 +626,7 @@ def row_batched(g, steps, with_oracle):
     batched()
     t_tuned = g.time_ms(lambda: [batched() for _ in range(steps)]) / steps
     prof = g.profile(batched)
+    prof_seq = g.profile(sequential)
     # algorithmic totals of one batched call: per-problem work summed
     totals = {}
     for q in specs:
@@ -696,6 +697,7 @@ def row_batched(g, steps, with_oracle):
         "roofline": rl, "rmse_final_mean": float(r_final.mean()),
         "oracle_teacher_forced_final_D": rec_oracle,
         "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+        "kernels_ms_sequential": {k: round(v[0], 3) for k, v in prof_seq.items() if v[1]},
         "small_problems": {
             "workload": "200 problems p=20 n=50 m=1500 s=3..5, 20 iterations",
             "value_batched": small_total / (t_sb / 1e3),

@@ -330,10 +330,16 @@ dl_status dl_iterate_proposed(const dl_params *prm, const dl_proposal *pr, const
 /* ---- batched independent problems -----------------------------------------
    Many independent problems of uneven (p, n, m, s) iterate together (the DL
    iteration of Alg. 1 with all atoms in one Jacobi group, eq. 2).  Every
-   stage of an iteration is one persistent launch over all problems: its
+   stage of an iteration is one persistent launch over the problems: its
    workgroups take (problem, tile) items from a device queue, larger problems
-   first; OMP runs one such launch per lane-group shape in use.  Each problem
-   gets bit-for-bit the results of dl_iterate with the same parameters. */
+   first; OMP runs one such launch per lane-group shape in use.  A problem
+   whose coding launch alone fills the GPU (a full round of three waves per
+   SIMD) runs instead with the launches of dl_iterate, on one of three
+   streams the library keeps per device (default priority), concurrently
+   with other such problems and with the shared launches; the caller's
+   stream waits for them before the call's work counts as done.  Each
+   problem gets bit-for-bit the results of dl_iterate with the same
+   parameters. */
 typedef struct dl_problem {
     dl_params prm;    /* FP32, group_size >= n and the AK-SVD or SGK rule only;
                          tolerances and OMP launch shape as for dl_iterate */
@@ -358,12 +364,14 @@ size_t dl_batch_workspace_size(const dl_problem *probs, int count);
 dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void *ws,
                              size_t ws_bytes, dl_stream_t stream);
 
-/* Autotuner of the OMP launch shape: for every distinct (p, n, s) it times
+/* Autotuner of the OMP launch shape of the problems that share the
+   persistent launches (those that run alone keep theirs): for every
+   distinct (p, n, s) among them it times
    each valid one-wave (omp_lanes_per_signal, omp_atoms_per_lane) with the
    OMP kernel of dl_iterate_batched on the largest such problem (its first
    65536 signals, correlations from its current D, `reps` timed launches
    after one warm-up, 1 <= reps <= 1000) and writes the
-   fastest into prm of every problem with that (p, n, s); the default shape
+   fastest into prm of every such problem with that (p, n, s); the default shape
    is kept unless another is at least 5% faster.  Synchronous;
    overwrites X_idx and X_val of the problems it times, not D.  Workspace as
    for dl_iterate_batched. */

@@ -20,22 +20,30 @@
 
 namespace dlk {
 
+static std::mutex g_occ_mu;
+
+// Compute units of the current device (queried once; 256 if the query fails).
+static int device_cus_locked()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 int batch_workers(const void *kernel, int block, size_t lds, int items)
 {
-    static std::mutex mu;
     static std::unordered_map<const void *, int> per_cu;
-    static int cus = 0;
-    int occ = 0;
+    int occ = 0, cus = 0;
     {
-        std::lock_guard<std::mutex> lock(mu);
-        if (cus == 0) {
-            int dev = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                    hipSuccess ||
-                cus <= 0)
-                cus = 256;
-        }
+        std::lock_guard<std::mutex> lock(g_occ_mu);
+        cus = device_cus_locked();
         auto it = per_cu.find(kernel);
         if (it != per_cu.end() && lds == 0) {
             occ = it->second;
@@ -94,6 +102,63 @@ OmpShape shape_of(const dl_params &q)
         sh.npl *= 2;
     }
     return sh;
+}
+
+// A problem whose coding launch alone holds a full round of waves (three per
+// SIMD) runs with its own single-problem launches, on one of the side
+// streams beside other such problems: sharing the persistent launches would
+// only add queue tickets and argument lookups to work that fills the GPU,
+// and the single-problem path has the launch shapes sized for it (two waves
+// per signal for large n and s, the error carried in the coding launch).
+// The smaller problems share the persistent launches on the caller's stream
+// (measured on 64 uneven problems: persistent launches for all of them ran
+// at 71 M signals*iters/s, one dl_iterate after another at 77 M).
+// Work of one coding pass (flop), to balance the side streams.
+double coding_work(const dl_params &q)
+{
+    return (double)q.m * ((double)q.n * (q.s * q.s + 3.0 * q.s) + 2.0 * q.p * q.n);
+}
+
+bool runs_alone(const dl_params &q)
+{
+    int cus;
+    {
+        std::lock_guard<std::mutex> lock(g_occ_mu);
+        cus = device_cus_locked();
+    }
+    // decided on the default launch shape, so that a shape the autotuner
+    // writes does not move a problem between the two groups
+    const int npl = omp_default_npl(q.n, q.s);
+    const int lps = omp_lanes_per_signal(q.n, npl, q.s);
+    const long long waves = lps > 64 ? 2ll * q.m : ((long long)q.m * lps + 63) / 64;
+    return waves >= 3ll * 4 * cus;
+}
+
+// Streams of the library for the problems that run alone: their iterations
+// are independent, so up to kSideStreams of them run at once, and the small
+// launches of one (CSR, update, error) overlap the others' work.  Created
+// once per device with the default priority, never destroyed.
+constexpr int kSideStreams = 3;
+
+hipError_t side_streams(hipStream_t *out)
+{
+    static std::mutex mu;
+    static std::unordered_map<int, std::vector<hipStream_t>> by_dev;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lock(mu);
+    std::vector<hipStream_t> &v = by_dev[dev];
+    while ((int)v.size() < kSideStreams) {
+        hipStream_t sd;
+        if ((e = hipStreamCreateWithFlags(&sd, hipStreamNonBlocking)) != hipSuccess)
+            return e;
+        v.push_back(sd);
+    }
+    for (int i = 0; i < kSideStreams; ++i)
+        out[i] = v[i];
+    return hipSuccess;
 }
 
 // Byte offsets of the batch workspace: queue, controls, tables and work
@@ -158,10 +223,11 @@ struct Plan {
 // Both parities of the per-problem arguments: in iteration k the dictionary
 // is read from buffer k % 2 (0 = the caller's D, 1 = the workspace's Dn) and
 // the update writes the other one.
-void build_plan(const dl_problem *probs, int count, char *base, const BatchLayout &L, Plan &P)
+void build_plan(const dl_problem *probs, const std::vector<int> &members, char *base,
+                const BatchLayout &L, Plan &P)
 {
-    std::vector<int> order(count);
-    std::iota(order.begin(), order.end(), 0);
+    const int count = (int)members.size();
+    std::vector<int> order(members);
     auto size_key = [&](int b) {
         const dl_params &q = probs[b].prm;
         return (long long)q.n * q.s * 1024 + q.p;
@@ -340,38 +406,30 @@ void build_plan(const dl_problem *probs, int count, char *base, const BatchLayou
             return DL_EHIP;                        \
     } while (0)
 
-extern "C" {
-
-size_t dl_batch_workspace_size(const dl_problem *probs, int count)
+// The caller's stream waits for everything enqueued on the side streams.
+hipError_t join_side_streams(hipStream_t st)
 {
-    if (!probs || count < 1 || count > kMaxProblems)
-        return 0;
-    for (int b = 0; b < count; ++b) {
-        const dl_params &q = probs[b].prm;
-        if (!params_ok(&q) || q.precision != DL_PREC_FP32 || q.group_size < q.n ||
-            q.rule == DL_RULE_NSGK)
-            return 0;
+    hipStream_t side[kSideStreams];
+    hipError_t e = side_streams(side);
+    for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) {
+        hipEvent_t done;
+        if ((e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess)
+            break;
+        e = hipEventRecord(done, side[i]);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(st, done, 0);
+        hipEventDestroy(done);
     }
-    return batch_layout(probs, count).total;
+    return e;
 }
 
-dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void *ws,
-                             size_t ws_bytes, dl_stream_t stream)
+// The problems of `shared` iterate together in persistent launches on st.
+dl_status iterate_shared(const dl_problem *probs, const std::vector<int> &shared, int iters,
+                         char *base, const BatchLayout &L, hipStream_t st)
 {
-    if (!probs || count < 1 || count > kMaxProblems || iters < 0 || !ws ||
-        ((uintptr_t)ws % 256) != 0)
-        return DL_EINVAL;
-    for (int b = 0; b < count; ++b)
-        if (!problem_ok(probs[b]) ||
-            (iters > 0 && (!probs[b].rmse || ((uintptr_t)probs[b].rmse % 8) != 0)))
-            return DL_EINVAL;
-    const BatchLayout L = batch_layout(probs, count);
-    if (ws_bytes < L.total)
-        return DL_EWORKSPACE;
-    char *base = (char *)ws;
-    hipStream_t st = (hipStream_t)stream;
     Plan P;
-    build_plan(probs, count, base, L, P);
+    build_plan(probs, shared, base, L, P);
+    const int count = (int)shared.size();
     const size_t c = (size_t)count;
     DL_TRY(hipMemcpyAsync(base + L.gemm, P.gemm.data(), sizeof(GemmPair) * 2 * c,
                           hipMemcpyHostToDevice, st));
@@ -423,13 +481,88 @@ dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void
         DL_TRY(launch_batched_rmse(rmse + (size_t)((iters - 1) & 1) * c, list(P.l_rmse, count),
                                    P.n_rmse, list(P.l_one, count), iters - 1, st));
     if (iters % 2 == 1)
-        for (int b = 0; b < count; ++b) {
+        for (int b : shared) {
             const dl_params &pq = probs[b].prm;
             const Layout W = layout_for(pq);
             DL_TRY(launch_copy(base + L.prob[b] + W.Dn, probs[b].D,
                                sizeof(float) * (size_t)pq.n * pq.p, st));
         }
     return DL_OK;
+}
+
+extern "C" {
+
+size_t dl_batch_workspace_size(const dl_problem *probs, int count)
+{
+    if (!probs || count < 1 || count > kMaxProblems)
+        return 0;
+    for (int b = 0; b < count; ++b) {
+        const dl_params &q = probs[b].prm;
+        if (!params_ok(&q) || q.precision != DL_PREC_FP32 || q.group_size < q.n ||
+            q.rule == DL_RULE_NSGK)
+            return 0;
+    }
+    return batch_layout(probs, count).total;
+}
+
+dl_status dl_iterate_batched(const dl_problem *probs, int count, int iters, void *ws,
+                             size_t ws_bytes, dl_stream_t stream)
+{
+    if (!probs || count < 1 || count > kMaxProblems || iters < 0 || !ws ||
+        ((uintptr_t)ws % 256) != 0)
+        return DL_EINVAL;
+    for (int b = 0; b < count; ++b)
+        if (!problem_ok(probs[b]) ||
+            (iters > 0 && (!probs[b].rmse || ((uintptr_t)probs[b].rmse % 8) != 0)))
+            return DL_EINVAL;
+    const BatchLayout L = batch_layout(probs, count);
+    if (ws_bytes < L.total)
+        return DL_EWORKSPACE;
+    char *base = (char *)ws;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int> shared, alone;
+    for (int b = 0; b < count; ++b)
+        (runs_alone(probs[b].prm) ? alone : shared).push_back(b);
+    if (!alone.empty()) {
+        // the problems that run alone go to the side streams, largest first,
+        // each to the stream with the least work so far; the side streams
+        // start after the caller's earlier work and the caller's stream
+        // waits for them at the end of the call
+        std::sort(alone.begin(), alone.end(), [&](int x, int y) {
+            return coding_work(probs[x].prm) > coding_work(probs[y].prm);
+        });
+        hipStream_t side[kSideStreams];
+        DL_TRY(side_streams(side));
+        hipEvent_t ev;
+        DL_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        hipError_t e = hipEventRecord(ev, st);
+        for (int i = 0; i < kSideStreams && e == hipSuccess; ++i)
+            e = hipStreamWaitEvent(side[i], ev, 0);
+        hipEventDestroy(ev);
+        DL_TRY(e);
+        double load[kSideStreams] = {0.0};
+        dl_status rc = DL_OK;
+        for (int b : alone) {
+            int i = 0;
+            for (int j = 1; j < kSideStreams; ++j)
+                if (load[j] < load[i])
+                    i = j;
+            load[i] += coding_work(probs[b].prm);
+            const dl_problem &pb = probs[b];
+            rc = dl_iterate(&pb.prm, pb.Y, pb.D, iters, pb.X_idx, pb.X_val, pb.rmse,
+                            base + L.prob[b], layout_for(pb.prm).total, side[i]);
+            if (rc != DL_OK)
+                break;
+        }
+        if (rc != DL_OK) {
+            join_side_streams(st);
+            return rc;
+        }
+    }
+    dl_status rc = shared.empty() ? DL_OK : iterate_shared(probs, shared, iters, base, L, st);
+    if (!alone.empty() && join_side_streams(st) != hipSuccess && rc == DL_OK)
+        rc = DL_EHIP;
+    return rc;
 }
 
 dl_status dl_autotune(dl_problem *probs, int count, int reps, void *ws, size_t ws_bytes,
@@ -456,14 +589,17 @@ dl_status dl_autotune(dl_problem *probs, int count, int reps, void *ws, size_t w
         return DL_EHIP;
     }
     dl_status rc = DL_OK;
+    // problems that run alone keep their shape (the single-problem launches)
     std::vector<bool> done(count, false);
+    for (int b = 0; b < count; ++b)
+        done[b] = runs_alone(probs[b].prm);
     for (int b0 = 0; b0 < count && rc == DL_OK; ++b0) {
         if (done[b0])
             continue;
         const dl_params &k0 = probs[b0].prm;
         auto same = [&](int b) {
             const dl_params &q = probs[b].prm;
-            return q.p == k0.p && q.n == k0.n && q.s == k0.s;
+            return !done[b] && q.p == k0.p && q.n == k0.n && q.s == k0.s;
         };
         int rep = b0;  // the largest problem of this (p, n, s)
         for (int b = b0; b < count; ++b)
