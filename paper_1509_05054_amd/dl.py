@@ -409,8 +409,10 @@ def iterate_batched(problems, iters, ws, stream=None):
 
 
 def autotune(problems, ws, reps=3, stream=None):
-    """Time the OMP launch shapes and store the fastest in every problem's
-    ``prm`` (``omp_lanes_per_signal``, ``omp_atoms_per_lane``); returns them."""
+    """Time the OMP launch shapes and store the fastest in the ``prm``
+    (``omp_lanes_per_signal``, ``omp_atoms_per_lane``) of every problem that
+    shares the persistent launches; returns every problem's shape ((0, 0):
+    the default, kept by the problems that run alone)."""
     arr = _problem_array(problems)
     _check(lib().dl_autotune(arr, len(problems), int(reps), _ptr(ws), ws.numel(),
                              _stream(stream)), "dl_autotune")
