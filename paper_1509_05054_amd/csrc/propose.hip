@@ -189,6 +189,7 @@ __device__ inline float lane_group_sum(float v)
 constexpr int kPruneBlock = 512;        // signals per block (8 waves)
 constexpr int kPruneLdsFloats = 16384;  // dictionaries up to 64 KB are staged in LDS
 constexpr int kPruneSlots = 32;         // LDS floats per signal: b, then (atom, x) pairs
+constexpr int RU = 4;                   // signals per lane group in flight in phases 1 and 3
 
 template <int K2, int LPU, bool DLDS>
 __global__ __launch_bounds__(kPruneBlock) __attribute__((amdgpu_waves_per_eu(2)))
@@ -220,29 +221,44 @@ void ls_prune_kernel(ProposeArgs a)
             sFbCount = 0;
         __syncthreads();  // the dictionary is staged; the previous block is done
 
-        // ---- phase 1: candidate correlations
-        for (int il0 = wave * GPW; il0 < kPruneBlock; il0 += NW * GPW) {
-            const int il = il0 + g;
-            const bool on = il < nsig;
-            const f32x4 y = (on && q < p)
-                                ? *reinterpret_cast<const f32x4 *>(a.Y + (size_t)(i0 + il) * p + q)
-                                : zero;
-            float part[K2];
+        // ---- phase 1: candidate correlations (RU signals per lane group at
+        // a time, so that their loads of y are in flight together)
+        for (int il0 = wave * GPW; il0 < kPruneBlock; il0 += NW * GPW * RU) {
+            f32x4 y[RU];
+            int cc[RU][K2];
 #pragma unroll
-            for (int t = 0; t < K2; ++t) {
-                int c = on ? a.cand[(size_t)(i0 + il) * K2 + t] : -1;
-                c = (c >= 0 && c < n) ? c : -1;
-                const f32x4 d =
-                    (c >= 0 && q < p) ? *reinterpret_cast<const f32x4 *>(Dr + (size_t)c * p + q) : zero;
-                part[t] = d[0] * y[0] + d[1] * y[1] + d[2] * y[2] + d[3] * y[3];
+            for (int u = 0; u < RU; ++u) {
+                const int il = il0 + u * NW * GPW + g;
+                const bool on = il < nsig;
+                y[u] = (on && q < p)
+                           ? *reinterpret_cast<const f32x4 *>(a.Y + (size_t)(i0 + il) * p + q)
+                           : zero;
+#pragma unroll
+                for (int t = 0; t < K2; ++t) {
+                    const int c = on ? a.cand[(size_t)(i0 + il) * K2 + t] : -1;
+                    cc[u][t] = (c >= 0 && c < n) ? c : -1;
+                }
             }
 #pragma unroll
-            for (int t = 0; t < K2; ++t)
-                part[t] = lane_group_sum<LPU>(part[t]);
-            if (on && l == 0)
+            for (int u = 0; u < RU; ++u) {
+                const int il = il0 + u * NW * GPW + g;
+                float part[K2];
+#pragma unroll
+                for (int t = 0; t < K2; ++t) {
+                    const int c = cc[u][t];
+                    const f32x4 d = (c >= 0 && q < p)
+                                        ? *reinterpret_cast<const f32x4 *>(Dr + (size_t)c * p + q)
+                                        : zero;
+                    part[t] = d[0] * y[u][0] + d[1] * y[u][1] + d[2] * y[u][2] + d[3] * y[u][3];
+                }
 #pragma unroll
                 for (int t = 0; t < K2; ++t)
-                    sBX[il * kPruneSlots + t] = part[t];
+                    part[t] = lane_group_sum<LPU>(part[t]);
+                if (il < nsig && l == 0)
+#pragma unroll
+                    for (int t = 0; t < K2; ++t)
+                        sBX[il * kPruneSlots + t] = part[t];
+            }
         }
         __syncthreads();
 
@@ -377,27 +393,37 @@ void ls_prune_kernel(ProposeArgs a)
         }
         __syncthreads();
 
-        // ---- phase 3: residual rows and the fallback test
-        for (int il0 = wave * GPW; il0 < kPruneBlock; il0 += NW * GPW) {
-            const int il = il0 + g;
-            const bool on = il < nsig;
-            const int i = i0 + (on ? il : 0);
-            f32x4 e = zero;
-            if (on && q < p)
-                e = *reinterpret_cast<const f32x4 *>(a.Y + (size_t)i * p + q);
-            const float *mine = sBX + (on ? il : 0) * kPruneSlots;
-            for (int t = 0; t < s; ++t) {
-                const int c = on ? __float_as_int(mine[2 * t]) : 0;
-                const float xv = on ? mine[2 * t + 1] : 0.f;
-                if (q < p)
-                    e -= *reinterpret_cast<const f32x4 *>(Dr + (size_t)c * p + q) * xv;
+        // ---- phase 3: residual rows and the fallback test (RU signals per
+        // lane group at a time)
+        for (int il0 = wave * GPW; il0 < kPruneBlock; il0 += NW * GPW * RU) {
+            f32x4 e[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int il = il0 + u * NW * GPW + g;
+                const bool on = il < nsig;
+                e[u] = (on && q < p)
+                           ? *reinterpret_cast<const f32x4 *>(a.Y + (size_t)(i0 + il) * p + q)
+                           : zero;
             }
-            if (on && q < p)
-                *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e;
-            const float enorm = sqrtf(lane_group_sum<LPU>(e[0] * e[0] + e[1] * e[1] +
-                                                          e[2] * e[2] + e[3] * e[3]));
-            if (on && l == 0 && (!sOk[il] || !(enorm <= (1.f + a.margin) * a.rref[i])))
-                sFb[atomicAdd(&sFbCount, 1)] = i;
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int il = il0 + u * NW * GPW + g;
+                const bool on = il < nsig;
+                const int i = i0 + (on ? il : 0);
+                const float *mine = sBX + (on ? il : 0) * kPruneSlots;
+                for (int t = 0; t < s; ++t) {
+                    const int c = on ? __float_as_int(mine[2 * t]) : 0;
+                    const float xv = on ? mine[2 * t + 1] : 0.f;
+                    if (q < p)
+                        e[u] -= *reinterpret_cast<const f32x4 *>(Dr + (size_t)c * p + q) * xv;
+                }
+                if (on && q < p)
+                    *reinterpret_cast<f32x4 *>(a.E + (size_t)i * p + q) = e[u];
+                const float enorm = sqrtf(lane_group_sum<LPU>(
+                    e[u][0] * e[u][0] + e[u][1] * e[u][1] + e[u][2] * e[u][2] + e[u][3] * e[u][3]));
+                if (on && l == 0 && (!sOk[il] || !(enorm <= (1.f + a.margin) * a.rref[i])))
+                    sFb[atomicAdd(&sFbCount, 1)] = i;
+            }
         }
         __syncthreads();
         const int cnt = sFbCount;
