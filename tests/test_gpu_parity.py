@@ -383,20 +383,26 @@ def test_iterate_free_running_full_size(gs):
     assert abs(gpu_rmse(w.Y, Dg, ig, vg) - rg[-1]) / rg[-1] < 1e-6
 
 
-@pytest.mark.parametrize("m,rule", [(3000, dl.RULE_AKSVD), (20000, dl.RULE_AKSVD),
-                                    (3000, dl.RULE_SGK), (20000, dl.RULE_SGK)])
-def test_iterate_refresh_in_error_pass_bitwise(m, rule):
+C2 = "patches_p64_n256_s6_m16384"
+
+
+@pytest.mark.parametrize("wl,m,rule", [(C2, 3000, dl.RULE_AKSVD), (C2, 20000, dl.RULE_AKSVD),
+                                       (C2, 3000, dl.RULE_SGK), (C2, 20000, dl.RULE_SGK),
+                                       ("patches_p256_n1024_s12_m65536", 3000, dl.RULE_AKSVD)])
+def test_iterate_refresh_in_error_pass_bitwise(wl, m, rule):
     """With all atoms in one group the iteration forms the refreshed X in the
     error pass; up to 16384 signals the error of iteration k is carried by
-    iteration k+1's products launch (partials, with the refresh) and CSR scan
-    launch (final sum), above that it runs in launches of its own (the SGK
-    rule keeps X).  Three iterations equal the explicit coding, update
-    (refresh in pass 2) and error calls of every iteration bit for bit: the
-    same errors of iterations 0 and 1 (carried at m = 3000) and 2 (always on
-    its own), the same dictionary after every iteration, and the same X."""
+    iteration k+1's coding launch (partials, with the refresh; X and E then
+    alternate between two buffers) or, for the two-wave coding shape (n =
+    1024, s = 12), by its products launch, and by its CSR scan launch (final
+    sum); above that it runs in launches of its own (the SGK rule keeps X).
+    Three iterations equal the explicit coding, update (refresh in pass 2)
+    and error calls of every iteration bit for bit: the same errors of
+    iterations 0 and 1 (carried at m = 3000) and 2 (always on its own), the
+    same dictionary after every iteration, and the same X."""
     iters = 3
-    w = synth.workload("patches_p64_n256_s6_m16384", m=m)
-    note(f"iterate refresh in error pass m={m} rule={rule} iters={iters}")
+    w = synth.workload(wl, m=m)
+    note(f"iterate refresh in error pass {wl} m={m} rule={rule} iters={iters}")
     prm = dl.Params(w.p, w.n, w.m, w.s, group_size=w.n, rule=rule)
     ws = dl.workspace(prm)
     Yg = dev(w.Y)
