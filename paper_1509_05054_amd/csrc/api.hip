@@ -26,6 +26,7 @@ Layout layout_for(const dl_params &prm)
     L.control = take(sizeof(Control));
     const size_t ldn = (size_t)padded_n(prm.n);
     L.G = take(sizeof(float) * n * ldn);
+    L.Gdiag = take(sizeof(float) * n);
     L.A0 = take(sizeof(float) * m * ldn);
     L.E = take(sizeof(float) * m * p);
     L.Dn = take(sizeof(float) * n * p);
@@ -134,9 +135,11 @@ dl_status check_ws(const dl_params *prm, const void *ws, size_t ws_bytes, Ws *ou
 // parameters ask for; rows of G and A0 have stride ldn.
 // prev_err: optional error partials of the previous iteration, computed by
 // extra workgroups of the grouped launch (independent of the products).
+// Gdiag (the coding's copy of G only): G's diagonal goes there and NaN to G's
+// diagonal.
 dl_status products(const dl_params &prm, const float *D, const float *Y, float *G, float *A0,
                    const Ws *ws, hipStream_t st, int ldn, const int32_t *m_dev = nullptr,
-                   const RmseArgs *prev_err = nullptr)
+                   const RmseArgs *prev_err = nullptr, float *Gdiag = nullptr)
 {
     if (prev_err && (!(G && A0) || !prev_err->Dold))
         return DL_EINVAL;  // the launch carries only the refreshing error pass
@@ -145,7 +148,7 @@ dl_status products(const dl_params &prm, const float *D, const float *Y, float *
         uint16_t *Ybf = ws->at<uint16_t>(ws->L.Ybf);
         DL_TRY(launch_cast_bf16(D, Dbf, (size_t)prm.n * prm.p, st));
         DL_TRY(launch_cast_bf16(Y, Ybf, (size_t)prm.m * prm.p, st));
-        const GemmBF16 g{Dbf, Dbf, G, prm.n, prm.n, prm.p, ldn, nullptr};
+        const GemmBF16 g{Dbf, Dbf, G, prm.n, prm.n, prm.p, ldn, nullptr, Gdiag};
         const GemmBF16 c{Ybf, Dbf, A0, prm.m, prm.n, prm.p, ldn, m_dev};
         if (G && A0)
             DL_TRY(launch_gemm_nt_bf16(g, &c, DL_K_CORR, st, prev_err));
@@ -154,7 +157,7 @@ dl_status products(const dl_params &prm, const float *D, const float *Y, float *
         else if (A0)
             DL_TRY(launch_gemm_nt_bf16(c, nullptr, DL_K_CORR, st));
     } else {
-        const GemmF32 g{D, D, G, prm.n, prm.n, prm.p, ldn, nullptr};
+        const GemmF32 g{D, D, G, prm.n, prm.n, prm.p, ldn, nullptr, Gdiag};
         const GemmF32 c{Y, D, A0, prm.m, prm.n, prm.p, ldn, m_dev};
         if (G && A0)
             DL_TRY(launch_gemm_nt_f32(g, &c, DL_K_CORR, st, prev_err));
@@ -190,7 +193,7 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
                                         prm.omp_atoms_per_lane);
     if (x.products) {
         dl_status rc = products(prm, D, Yin, G, A0, &ws, st, padded_n(prm.n), nullptr,
-                                err_in_coding ? nullptr : x.prev_err);
+                                err_in_coding ? nullptr : x.prev_err, ws.at<float>(ws.L.Gdiag));
         if (rc != DL_OK)
             return rc;
     }
@@ -199,6 +202,7 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
     OmpArgs a;
     a.A0 = A0;
     a.G = G;
+    a.Gdiag = ws.at<float>(ws.L.Gdiag);
     a.Y = Yin;
     a.D = D;
     a.idx = idx;
@@ -640,7 +644,8 @@ static dl_status code_proposed(const dl_params &q, const dl_proposal &pr, const 
     int32_t *fb_list = (int32_t *)((char *)pws + align256(sizeof(int32_t) * 64));
     float *Y_fb = (float *)((char *)fb_list + align256(sizeof(int32_t) * (size_t)q.m));
     float *G = w.at<float>(w.L.G);
-    dl_status rc = products(q, D, Y, G, nullptr, &w, st, padded_n(q.n));
+    dl_status rc = products(q, D, Y, G, nullptr, &w, st, padded_n(q.n), nullptr, nullptr,
+                            w.at<float>(w.L.Gdiag));
     if (rc != DL_OK)
         return rc;
     DL_TRY(launch_zero(fb_count, 4, st));
@@ -648,6 +653,7 @@ static dl_status code_proposed(const dl_params &q, const dl_proposal &pr, const 
     a.Y = Y;
     a.D = D;
     a.G = G;
+    a.Gdiag = w.at<float>(w.L.Gdiag);
     a.cand = pr.cand;
     a.rref = rref;
     a.idx = X_idx;

@@ -259,7 +259,7 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
             const float *Dc = Dbuf[par];
             float *Dx = Dbuf[par ^ 1];
             GemmPair gp;
-            gp.g = GemmF32{Dc, Dc, f(W.G), q.n, q.n, q.p, ldn, nullptr};
+            gp.g = GemmF32{Dc, Dc, f(W.G), q.n, q.n, q.p, ldn, nullptr, f(W.Gdiag)};
             gp.c = GemmF32{pb.Y, Dc, f(W.A0), q.m, q.n, q.p, ldn, nullptr};
             P.gemm[par * count + r] = gp;
             UpdateArgs u;
@@ -371,6 +371,7 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
                 memset(&a, 0, sizeof(a));
                 a.A0 = gp.c.C;
                 a.G = gp.g.C;
+                a.Gdiag = gp.g.diag;
                 a.Y = probs[b].Y;
                 a.D = u.D;
                 a.idx = probs[b].X_idx;
@@ -612,7 +613,8 @@ dl_status dl_autotune(dl_problem *probs, int count, int reps, void *ws, size_t w
         float *G = reinterpret_cast<float *>(wb + W.G);
         float *A0 = reinterpret_cast<float *>(wb + W.A0);
         const int ldn = padded_n(q.n);
-        const GemmF32 g{pb.D, pb.D, G, q.n, q.n, q.p, ldn, nullptr};
+        const GemmF32 g{pb.D, pb.D, G, q.n, q.n, q.p, ldn, nullptr,
+                        reinterpret_cast<float *>(wb + W.Gdiag)};
         const GemmF32 cr{pb.Y, pb.D, A0, q.m, q.n, q.p, ldn, nullptr};
         if (launch_gemm_nt_f32(g, &cr, DL_K_CORR, st) != hipSuccess) {
             rc = DL_EHIP;
@@ -622,6 +624,7 @@ dl_status dl_autotune(dl_problem *probs, int count, int reps, void *ws, size_t w
         memset(&a, 0, sizeof(a));
         a.A0 = A0;
         a.G = G;
+        a.Gdiag = g.diag;
         a.Y = pb.Y;
         a.D = pb.D;
         a.idx = pb.X_idx;

@@ -35,7 +35,8 @@ struct Control {
 // Byte offsets of the workspace regions (each 256-byte aligned).
 struct Layout {
     size_t control;
-    size_t G;          // [n][n] float
+    size_t G;          // [n][n] float, NaN on the diagonal (the coding's copy)
+    size_t Gdiag;      // [n] float, the diagonal of G
     size_t A0;         // [m][n] float, D^T y per signal
     size_t E;          // [m][p] float, residual
     size_t Dn;         // [n][p] float, next dictionary
@@ -71,17 +72,23 @@ void prof_end(int kernel, hipStream_t st);
 // ---- launchers (return hipSuccess or the launch error) -------------------
 // C[M][N] (row stride ldc) = A[M][K] * B[N][K]^T on MFMA with FP32
 // accumulation; K % 4 == 0.  Up to two independent problems share a launch.
+// diag (optional, Gram matrices only): the diagonal C_ii is stored there and
+// C_ii itself is set to NaN.  The coding reads G rows with the selected atom's
+// own entry NaN: its correlation then turns NaN in the step's update and stays
+// so, which no comparison selects again, so the argmax needs no mask.
 struct GemmF32 {
     const float *A, *B;
     float *C;
     int M, N, K, ldc;
     const int32_t *M_dev;  // optional: rows read on the device (<= M)
+    float *diag = nullptr;
 };
 struct GemmBF16 {  // BF16 inputs as uint16 bit patterns
     const uint16_t *A, *B;
     float *C;
     int M, N, K, ldc;
     const int32_t *M_dev;
+    float *diag = nullptr;
 };
 struct RmseArgs;
 // err: optional error partials (rmse_blocks(err->m) workgroups of the
@@ -95,7 +102,8 @@ hipError_t launch_cast_bf16(const float *x, uint16_t *y, size_t count, hipStream
 
 struct OmpArgs {
     const float *A0;   // [m][n]
-    const float *G;    // [n][n]
+    const float *G;    // [n][n], NaN on the diagonal
+    const float *Gdiag;  // [n] the diagonal of G
     const float *Y;    // [m][p]
     const float *D;    // [n][p]
     int32_t *idx;      // [m][s]
@@ -237,7 +245,8 @@ hipError_t launch_topk(const float *logits, int rows, int cols, int k, int32_t *
                        hipStream_t st);
 
 struct ProposeArgs {
-    const float *Y, *D, *G;    // [m][p], [n][p], [n][ldn]
+    const float *Y, *D, *G;    // [m][p], [n][p], [n][ldn] (NaN on the diagonal)
+    const float *Gdiag;        // [n] the diagonal of G
     const int32_t *cand;       // [m][k2]
     const float *rref;         // [m] reference OMP residual norms
     int32_t *idx;              // [m][s]

@@ -33,7 +33,7 @@ constexpr int kStageLd = kBlockN + 4;
 
 template <int TM, int BM>
 __device__ inline void store_block(float *C, int M, int N, int ldc, int brow0, int bcol0,
-                                   const f32x4 (&acc)[TM][kTN], float *sC)
+                                   const f32x4 (&acc)[TM][kTN], float *sC, float *diag)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -58,7 +58,11 @@ __device__ inline void store_block(float *C, int M, int N, int ldc, int brow0, i
         const int row = brow0 + rr;
         if (row >= M || col >= N)
             continue;
-        const f32x4 v = *reinterpret_cast<const f32x4 *>(sC + rr * kStageLd + cc);
+        f32x4 v = *reinterpret_cast<const f32x4 *>(sC + rr * kStageLd + cc);
+        if (diag && row >= col && row < col + 4) {
+            diag[row] = v[row - col];
+            v[row - col] = __builtin_nanf("");
+        }
         float *dst = C + (size_t)row * ldc + col;
         if (vec_ok && col + 3 < N) {
             *reinterpret_cast<f32x4 *>(dst) = v;
@@ -200,7 +204,7 @@ __device__ inline void gemm_f32_tile(const GemmF32 &P, int brow0, int bcol0)
         }
     }
     __syncthreads();  // the output stage overwrites the operand stages
-    store_block<TM, BM>(P.C, M, N, P.ldc, brow0, bcol0, acc, lds);
+    store_block<TM, BM>(P.C, M, N, P.ldc, brow0, bcol0, acc, lds, P.diag);
 }
 
 // Workgroup tiles of 128 rows (TM = 4) for the batched products and the
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmBF16 p0, GemmBF16
         }
     }
     __syncthreads();  // the output stage overwrites the operand stages
-    store_block<TM, BM>(P.C, M, N, P.ldc, brow0, bcol0, acc, lds);
+    store_block<TM, BM>(P.C, M, N, P.ldc, brow0, bcol0, acc, lds, P.diag);
 }
 
 // Round-to-nearest-even FP32 -> BF16 on the bit pattern (NaN kept quiet).

@@ -201,15 +201,17 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
     const float ynorm = sqrtf(group_sum<LPS>(ysq));
     const float thr = a.tol_corr * ynorm;
 
-    // correlations of y; atoms beyond n are marked as taken
+    // correlations of y.  A selected atom's correlation turns NaN in the
+    // step's update (G holds NaN on its diagonal, so u_k is NaN there) and
+    // stays NaN, and no comparison picks a NaN: the argmax needs no mask.
+    // Atoms beyond n start as NaN.
     const int a_first = (wsub * LPS + l) * NPL;
     vec_t<NPL> alpha;
     load_row<NPL>(alpha, a.A0 + (size_t)i * ldn, a_first, ldn, valid);
-    unsigned taken = 0;
 #pragma unroll
     for (int c = 0; c < NPL; ++c)
         if (a_first + c >= n)
-            taken |= 1u << c;
+            alpha[c] = __builtin_nanf("");
 
     vec_t<NPL> u[US];
     float Lrow[SMAX];     // row l of L (this lane's row)
@@ -236,13 +238,13 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         constexpr int k = decltype(kc)::value;
         if (k >= s || !__any(active))
             return false;
-        // 1. masked argmax over the group, lowest index on ties
+        // 1. argmax over the group (selected atoms are NaN), lowest index on ties
         float best = -1.f;
         int bidx = 0x7fffffff;
 #pragma unroll
         for (int c = 0; c < NPL; ++c) {
             const float v = fabsf(alpha[c]);
-            const bool b = !((taken >> c) & 1u) && v > best;
+            const bool b = v > best;
             best = b ? v : best;
             bidx = b ? a_first + c : bidx;
         }
@@ -262,10 +264,10 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         const int j = ok ? bidx : 0;
         const float *Gj = a.G + (size_t)j * ldn;
 
-        // 2. loads for this step: the G row, G_jj, A0_j, and G[j][I_l]
+        // 2. loads for this step: the G row (NaN at j), G_jj, A0_j, and G[j][I_l]
         vec_t<NPL> g;
         load_row<NPL>(g, Gj, a_first, ldn, ok);
-        const float gjj = ok ? Gj[j] : 1.f;
+        const float gjj = ok ? a.Gdiag[j] : 1.f;
         const float a0j = ok ? a.A0[(size_t)i * ldn + j] : 0.f;
         float acc = (ok && l < k) ? Gj[selj] : 0.f;
 
@@ -361,8 +363,6 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
             }
         }
         if (ok) {
-            if (wsub * LPS + l == j / NPL)  // the lane holding atom j
-                taken |= 1u << (j % NPL);
 #pragma unroll
             for (int t = 0; t < SMAX; ++t)
                 if (t == k) {

@@ -281,7 +281,8 @@ void ls_prune_kernel(ProposeArgs a)
             for (int r = 0; r < K2; ++r)
 #pragma unroll
                 for (int qq = 0; qq <= r; ++qq)
-                    Gc[tri(r, qq)] = a.G[(size_t)c[r] * ldn + c[qq]];
+                    Gc[tri(r, qq)] = c[r] == c[qq] ? a.Gdiag[c[r]]  // G holds NaN there
+                                                   : a.G[(size_t)c[r] * ldn + c[qq]];
             int kept = 0;
 #pragma unroll
             for (int t = 0; t < K2; ++t)
