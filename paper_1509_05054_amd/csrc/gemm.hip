@@ -47,6 +47,16 @@ __device__ inline void store_block(float *C, int M, int N, int ldc, int brow0, i
                 sC[(wr + 16 * a + 4 * (lane >> 4) + r) * kStageLd + wc + 16 * b + (lane & 15)] =
                     acc[a][b][r];
     __syncthreads();
+    if (diag) {  // a Gram tile: its diagonal entries go to diag, NaN to C
+        const int d0 = max(brow0, bcol0);
+        const int d1 = min(min(brow0 + BM, bcol0 + kBlockN), min(M, N));
+        for (int r = d0 + (int)threadIdx.x; r < d1; r += (int)blockDim.x) {
+            float *e = sC + (r - brow0) * kStageLd + (r - bcol0);
+            diag[r] = *e;
+            *e = __builtin_nanf("");
+        }
+        __syncthreads();
+    }
     // 32 lanes per row, 4 columns each: 8 rows per pass of the workgroup;
     // 16-byte stores when C and its row stride allow them
     const bool vec_ok = (ldc % 4) == 0 && ((uintptr_t)C % 16) == 0;
@@ -58,11 +68,7 @@ __device__ inline void store_block(float *C, int M, int N, int ldc, int brow0, i
         const int row = brow0 + rr;
         if (row >= M || col >= N)
             continue;
-        f32x4 v = *reinterpret_cast<const f32x4 *>(sC + rr * kStageLd + cc);
-        if (diag && row >= col && row < col + 4) {
-            diag[row] = v[row - col];
-            v[row - col] = __builtin_nanf("");
-        }
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(sC + rr * kStageLd + cc);
         float *dst = C + (size_t)row * ldc + col;
         if (vec_ok && col + 3 < N) {
             *reinterpret_cast<f32x4 *>(dst) = v;
