@@ -112,6 +112,14 @@ __device__ inline float group_bcast(float v)
 {
     if constexpr (LPS == 64) {
         return bits_f(__builtin_amdgcn_readlane(f_bits(v), R));
+    } else if constexpr (LPS == 16) {
+        // DPP row_newbcast: lane R of every row of 16 (measured 3% faster
+        // coding than the swizzle at m = 16384)
+        return bits_f(__builtin_amdgcn_mov_dpp(f_bits(v), 0x150 + R, 0xF, 0xF, false));
+    } else if constexpr (LPS == 4) {
+        // DPP quad_perm [R, R, R, R]
+        return bits_f(__builtin_amdgcn_mov_dpp(f_bits(v), R | (R << 2) | (R << 4) | (R << 6), 0xF,
+                                               0xF, false));
     } else {
         // ds_swizzle bit mode inside 32 lanes: source = (lane & and) | or
         constexpr int and_mask = 31 & ~(LPS - 1);
