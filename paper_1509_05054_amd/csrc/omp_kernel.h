@@ -53,6 +53,15 @@ __device__ inline int dpp(int v)
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
+// The same with bound control set, which lets the compiler fold the move into
+// the VALU instruction that consumes it (every pattern used here reads lanes
+// inside the row, so no lane is out of bounds).
+template <int CTRL>
+__device__ inline int dpp_fold(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+
 // A DPP lane permutation that every lane takes part in (no bound control).
 template <int CTRL>
 __device__ inline int dpp_all(int v)
@@ -68,6 +77,38 @@ __device__ inline void take_better(float &v, int &ix, float ov, int oi)
     const bool b = (ov > v) | ((ov == v) & (oi < ix));
     v = b ? ov : v;
     ix = b ? oi : ix;
+}
+
+// All-reduce over groups of LPS lanes: the maximum of v, then the lowest
+// index among the lanes that hold it.  v is -1 or a non-negative float (never
+// NaN), whose order is that of its bits as signed integers, so both are
+// integer reductions; two plain reductions take fewer instructions than one
+// over (value, index) pairs.
+template <int LPS>
+__device__ inline int group_min_max(int x, bool take_max)
+{
+    auto pick = [&](int a, int b) { return take_max ? max(a, b) : min(a, b); };
+    if constexpr (LPS >= 2)
+        x = pick(x, dpp_fold<0xB1>(x));
+    if constexpr (LPS >= 4)
+        x = pick(x, dpp_fold<0x4E>(x));
+    if constexpr (LPS >= 8)
+        x = pick(x, dpp_fold<0x141>(x));
+    if constexpr (LPS >= 16)
+        x = pick(x, dpp_fold<0x140>(x));
+    if constexpr (LPS >= 32)
+        x = pick(x, __shfl_xor(x, 16));
+    if constexpr (LPS >= 64)
+        x = pick(x, __shfl_xor(x, 32));
+    return x;
+}
+
+template <int LPS>
+__device__ inline void group_argmax_split(float &v, int &ix)
+{
+    const int gmax = group_min_max<LPS>(f_bits(v), true);
+    ix = group_min_max<LPS>(f_bits(v) == gmax ? ix : 0x7fffffff, false);
+    v = bits_f(gmax);
 }
 
 // All-reduce of (max value, lowest index) over groups of LPS lanes.
@@ -256,7 +297,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
             best = b ? v : best;
             bidx = b ? a_first + c : bidx;
         }
-        group_argmax<LPS>(best, bidx);
+        group_argmax_split<LPS>(best, bidx);
         if constexpr (WPS == 2) {
             if (l == 0) {
                 sPairV[k & 1][wsub] = best;
