@@ -53,20 +53,13 @@ __device__ inline int dpp(int v)
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
-// The same with bound control set, which lets the compiler fold the move into
-// the VALU instruction that consumes it (every pattern used here reads lanes
-// inside the row, so no lane is out of bounds).
+// A DPP lane permutation with bound control set, which lets the compiler fold
+// the move into the VALU instruction that consumes it (every pattern used
+// here reads lanes inside the row, so no lane is out of bounds).
 template <int CTRL>
 __device__ inline int dpp_fold(int v)
 {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
-}
-
-// A DPP lane permutation that every lane takes part in (no bound control).
-template <int CTRL>
-__device__ inline int dpp_all(int v)
-{
-    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
 }
 
 // Combine (value, index) pairs: larger value wins, lower index on ties
@@ -104,29 +97,11 @@ __device__ inline int group_min_max(int x, bool take_max)
 }
 
 template <int LPS>
-__device__ inline void group_argmax_split(float &v, int &ix)
+__device__ inline void group_argmax(float &v, int &ix)
 {
     const int gmax = group_min_max<LPS>(f_bits(v), true);
     ix = group_min_max<LPS>(f_bits(v) == gmax ? ix : 0x7fffffff, false);
     v = bits_f(gmax);
-}
-
-// All-reduce of (max value, lowest index) over groups of LPS lanes.
-template <int LPS>
-__device__ inline void group_argmax(float &v, int &ix)
-{
-    if constexpr (LPS >= 2)
-        take_better(v, ix, bits_f(dpp_all<0xB1>(f_bits(v))), dpp_all<0xB1>(ix));    // lane ^ 1
-    if constexpr (LPS >= 4)
-        take_better(v, ix, bits_f(dpp_all<0x4E>(f_bits(v))), dpp_all<0x4E>(ix));    // lane ^ 2
-    if constexpr (LPS >= 8)
-        take_better(v, ix, bits_f(dpp_all<0x141>(f_bits(v))), dpp_all<0x141>(ix));  // half-row mirror
-    if constexpr (LPS >= 16)
-        take_better(v, ix, bits_f(dpp_all<0x140>(f_bits(v))), dpp_all<0x140>(ix));  // row mirror
-    if constexpr (LPS >= 32)
-        take_better(v, ix, __shfl_xor(v, 16), __shfl_xor(ix, 16));
-    if constexpr (LPS >= 64)
-        take_better(v, ix, __shfl_xor(v, 32), __shfl_xor(ix, 32));
 }
 
 template <int LPS>
@@ -297,7 +272,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
             best = b ? v : best;
             bidx = b ? a_first + c : bidx;
         }
-        group_argmax_split<LPS>(best, bidx);
+        group_argmax<LPS>(best, bidx);
         if constexpr (WPS == 2) {
             if (l == 0) {
                 sPairV[k & 1][wsub] = best;
