@@ -184,6 +184,41 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
     const int sub = lane / lpu;
     const int q = 4 * (lane % lpu);
     const int t = threadIdx.x;  // coordinate of d_j' owned by this thread
+    if (a.no_refresh) {
+        // d' only (the error pass refreshes X): item blk takes atoms blk,
+        // blk + nblk, ... of the group, each summing its chunk partials in
+        // chunk order; atoms without users keep d_j
+        for (int j = a0 + blk; j < a1; j += nblk) {
+            const int c0 = a.chunk_ptr[j], c1 = a.chunk_ptr[j + 1];
+            if (c0 == c1) {  // uniform
+                for (int k = t; k < p; k += blockDim.x)
+                    a.Dn[(size_t)j * p + k] = a.D[(size_t)j * p + k];
+                if (t == 0) {
+                    a.atom_state[j] = 1;
+                    atomicAdd(&a.ctl->unused_atoms, 1ull);
+                }
+                continue;
+            }
+            float g = 0.f;
+            if (t < p)
+                for (int cc = c0; cc < c1; ++cc)
+                    g += a.partial[(size_t)cc * p + t];
+            const float sq = block_sum_f32(g * g, red4);
+            const int state = sq > 0.f ? 0 : 2;
+            const float inv = state == 0 ? 1.0f / sqrtf(sq) : 0.f;
+            if (t < p)
+                a.Dn[(size_t)j * p + t] = state == 0 ? g * inv : a.D[(size_t)j * p + t];
+            if (t == 0) {
+                a.atom_state[j] = state;
+                if (state == 2) {
+                    atomicAdd(&a.ctl->zero_updates, 1ull);
+                    if (!(sq == 0.f))
+                        atomicAdd(&a.ctl->nonfinite, 1ull);
+                }
+            }
+        }
+        return;
+    }
     const int cbase = a.chunk_ptr[a0];
     const int nch = a.chunk_ptr[a1] - cbase;
     for (int c = blk; c < nch; c += nblk) {
@@ -531,10 +566,12 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
         // residual rows in flight per lane: 8 for short signals, 4 for long
         // ones (measured: 8 is 5% faster at p = 64 and 20% slower at p = 256,
         // where the 8-row kernel holds more registers)
+        // with the refresh in the error pass, pass 2 takes one item per atom
+        const unsigned g2 = a.no_refresh ? (unsigned)(a1 - a0 < 2048 ? a1 - a0 : 2048) : grid;
         if (a.p <= 64)
-            hipLaunchKernelGGL(pass2_kernel<0>, dim3(grid), dim3(256), 0, st, a, a0, a1);
+            hipLaunchKernelGGL(pass2_kernel<0>, dim3(g2), dim3(256), 0, st, a, a0, a1);
         else
-            hipLaunchKernelGGL(pass2_kernel<4>, dim3(grid), dim3(256), 0, st, a, a0, a1);
+            hipLaunchKernelGGL(pass2_kernel<4>, dim3(g2), dim3(256), 0, st, a, a0, a1);
         prof_end(DL_K_UPD_PASS2, st);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
