@@ -150,6 +150,40 @@ def test_batched_mixed_alone_and_shared():
     assert shapes[0] == (0, 0) and shapes[2] == (0, 0) and shapes[4] == (0, 0), shapes
 
 
+def test_batched_orders_on_the_callers_stream():
+    """The problems that run alone go to the library's own streams; the call
+    still orders like one launch sequence on the caller's stream: it starts
+    after the caller's earlier work there (here the copy of the initial
+    dictionaries, behind a long kernel) and later work on that stream sees its
+    results, with only that stream synchronised."""
+    specs = [_tiny(64, 256, 20000, 6, 21), _tiny(64, 256, 3000, 6, 22),
+             _tiny(64, 256, 14000, 6, 23)]
+    note("batched call ordered on a caller's stream")
+    probs = _problems(specs, 2)
+    ws = dl.batch_workspace(probs)
+    side = torch.cuda.Stream()
+    D0s = [dev(q["D0"]) for q in specs]
+    for pb in probs:
+        pb.D.fill_(float("nan"))
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        big = torch.randn(4096, 4096, device="cuda")
+        for _ in range(4):
+            big = big @ big.T / 4096.0  # keeps the stream busy before the copies
+        for pb, d0 in zip(probs, D0s):
+            pb.D.copy_(d0)
+        dl.iterate_batched(probs, 2, ws, stream=side)
+        outs = [(pb.D.clone(), pb.X_idx.clone(), pb.X_val.clone(), pb.rmse.clone())
+                for pb in probs]
+    side.synchronize()
+    for k, q in enumerate(specs):
+        D, idx, val, r = _single(q, 2, probs[k].prm)
+        np.testing.assert_array_equal(host(outs[k][0]), D, err_msg=str(k))
+        np.testing.assert_array_equal(host(outs[k][1]), idx, err_msg=str(k))
+        np.testing.assert_array_equal(host(outs[k][2]), val, err_msg=str(k))
+        np.testing.assert_array_equal(host(outs[k][3])[:2], r[:2], err_msg=str(k))
+
+
 def test_full_batch_of_uneven_problems():
     """The 64-problem batch at full size for two iterations; a spread of its
     problems is checked bit-for-bit against the single-problem path."""
