@@ -249,6 +249,7 @@ dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, in
     c.n = prm.n;
     c.m = prm.m;
     c.s = prm.s;
+    c.chunk = chunk_users(prm);
     DL_TRY(launch_csr(c, st, prev_err));
     return DL_OK;
 }
@@ -289,6 +290,7 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
     u.rule = prm.rule;
     u.max_chunks = max_chunks(prm);
     u.no_refresh = error_refreshes ? 1 : 0;
+    u.chunk = chunk_users(prm);
     DL_TRY(launch_update(u, st));
     return DL_OK;
 }

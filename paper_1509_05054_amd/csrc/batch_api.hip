@@ -284,6 +284,7 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
             u.group_size = q.n;
             u.rule = q.rule;
             u.max_chunks = max_chunks(q);
+            u.chunk = chunk_users(q);
             P.upd[par * count + r] = u;
             RmseArgs rm;
             rm.Y = pb.Y;
@@ -314,6 +315,7 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
         cs.n = q.n;
         cs.m = q.m;
         cs.s = q.s;
+        cs.chunk = chunk_users(q);
         P.csr[r] = cs;
         P.norm[r] = NormArgs{pb.D, q.n, q.p, c};
         it_gemm[r] = gemm_pair_items(P.gemm[r]);

@@ -12,7 +12,7 @@
 //             its total.
 //   scatter : every workgroup scans the atom totals into atom offsets in LDS
 //             (the first also writes row_ptr and chunk_ptr, the update's
-//             chunks of kChunk users); one thread per entry:
+//             chunks of the update's chunk size); one thread per entry:
 //             users[row offset + block offset + rank] = entry.
 // Entries of an atom end up in increasing (signal, slot) order, so the
 // result is unique and the atom update's summation order is fixed.
@@ -152,12 +152,12 @@ __device__ inline void csr_scan_body(int32_t *__restrict__ blkcnt, int32_t *__re
 }
 
 // Exclusive scan of the atom totals into sRow[0..n] (users) and, when
-// chunk_ptr is given, of their chunk counts (kChunk users per chunk) into
+// chunk_ptr is given, of their chunk counts (chunk users per chunk) into
 // chunk_ptr, and sRow into row_ptr; 256 threads, thread t owning atoms
 // [t*per, (t+1)*per).
 __device__ inline void csr_prefix_block(const int32_t *__restrict__ tot, int n, int32_t *sRow,
                                         int32_t *__restrict__ row_ptr,
-                                        int32_t *__restrict__ chunk_ptr)
+                                        int32_t *__restrict__ chunk_ptr, int chunk)
 {
     __shared__ int sh[2][4];
     const int lane = threadIdx.x & 63;
@@ -170,7 +170,7 @@ __device__ inline void csr_prefix_block(const int32_t *__restrict__ tot, int n, 
         if (aa < n) {
             const int v = tot[aa];
             su += v;
-            sc += (v + kChunk - 1) / kChunk;
+            sc += (v + chunk - 1) / chunk;
         }
     }
     const int xu = wave_inclusive_scan(su);
@@ -201,7 +201,7 @@ __device__ inline void csr_prefix_block(const int32_t *__restrict__ tot, int n, 
                 chunk_ptr[aa] = rc;
             }
             ru += v;
-            rc += (v + kChunk - 1) / kChunk;
+            rc += (v + chunk - 1) / chunk;
         }
     }
     if (threadIdx.x == 0) {
@@ -240,10 +240,10 @@ __device__ inline void csr_scatter_body(const int32_t *__restrict__ idx,
                                         int32_t *__restrict__ users, int2 *__restrict__ uent,
                                         const float *__restrict__ val,
                                         float *__restrict__ val_pad, int n, int m, int s, int nb,
-                                        int blk, int nblk)
+                                        int chunk, int blk, int nblk)
 {
     __shared__ int32_t sRow[1025];
-    csr_prefix_block(tot, n, sRow, row_ptr, blk == 0 ? chunk_ptr : nullptr);
+    csr_prefix_block(tot, n, sRow, row_ptr, blk == 0 ? chunk_ptr : nullptr, chunk);
     const size_t total = (size_t)m * s;
     for (size_t pos = (size_t)blk * blockDim.x + threadIdx.x; pos < total;
          pos += (size_t)nblk * blockDim.x) {
@@ -267,11 +267,10 @@ __global__ __launch_bounds__(256) void csr_scatter_kernel(
     const int32_t *__restrict__ tot, int32_t *__restrict__ row_ptr,
     int32_t *__restrict__ chunk_ptr, const int32_t *__restrict__ lrank,
     int32_t *__restrict__ users, int2 *__restrict__ uent, const float *__restrict__ val,
-    float *__restrict__ val_pad, int n, int m, int s, int nb)
+    float *__restrict__ val_pad, int n, int m, int s, int nb, int chunk)
 {
     csr_scatter_body(idx, blkoff, tot, row_ptr, chunk_ptr, lrank, users, uent, val, val_pad, n,
-                     m, s, nb,
-                     blockIdx.x, gridDim.x);
+                     m, s, nb, chunk, blockIdx.x, gridDim.x);
 }
 
 // ---- batched problems: one launch per pass over every problem's items ----
@@ -337,8 +336,8 @@ __global__ __launch_bounds__(256) void csr_scatter_batched(const CsrArgs *__rest
         if (batch_owner(bl.start, bl.count, cur.it, own))
             a = tab[own.b];
         csr_scatter_body(a.idx, a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.lrank, a.users,
-                         a.uent, a.val, a.val_pad, a.n, a.m, a.s, csr_nb(a.m), cur.it - own.b0,
-                         own.b1 - own.b0);
+                         a.uent, a.val, a.val_pad, a.n, a.m, a.s, csr_nb(a.m), a.chunk,
+                         cur.it - own.b0, own.b1 - own.b0);
     }
     if (threadIdx.x == 0)
         batch_leave(bl.q, gridDim.x);
@@ -405,7 +404,7 @@ hipError_t launch_csr(const CsrArgs &a, hipStream_t st, const RmseArgs *err)
     prof_begin(DL_K_CSR_SCATTER, st);
     hipLaunchKernelGGL(csr_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a.idx,
                        a.blkcnt, a.tot, a.row_ptr, a.chunk_ptr, a.lrank, a.users, a.uent, a.val,
-                       a.val_pad, a.n, a.m, a.s, nb);
+                       a.val_pad, a.n, a.m, a.s, nb, a.chunk);
     prof_end(DL_K_CSR_SCATTER, st);
     return hipGetLastError();
 }

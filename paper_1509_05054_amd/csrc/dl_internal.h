@@ -11,7 +11,7 @@
 namespace dlk {
 
 // Users of one atom are processed in chunks of this many (atom update).
-constexpr int kChunk = 256;
+constexpr int kChunk = 256;  // most users per chunk of the atom update
 // Signals per block of the CSR transpose (one workgroup each).
 constexpr int kCsrBlock = 256;
 // Signals per workgroup of the FP64 error reduction.
@@ -63,6 +63,12 @@ Layout layout_for(const dl_params &prm);
 bool params_ok(const dl_params *prm);
 int csr_blocks(int m);
 int max_chunks(const dl_params &prm);
+// Users per chunk of the atom update: kChunk with all atoms in one group;
+// half that with smaller groups, whose atoms have fewer users each (measured
+// at group size 16, m = 16384: 39.6 -> 47.3 M signals*iters/s; with one
+// group the larger chunks stay faster, 282 vs 279 M, and at m = 262144
+// 483 vs 468 M).
+int chunk_users(const dl_params &prm);
 int rmse_blocks(int m);
 
 // Optional per-kernel timing (dl_profile_enable): bracket a launch.
@@ -142,6 +148,7 @@ struct CsrArgs {
     const float *val;    // coefficients [m][s] (with uent)
     float *val_pad;      // optional: zero written at padding slots
     int n, m, s;
+    int chunk = kChunk;  // users per chunk of the atom update (chunk_ptr)
 };
 // err: optional error whose partials are complete; its final sum runs as one
 // extra workgroup of the scan launch.
@@ -162,6 +169,7 @@ struct UpdateArgs {
     Control *ctl;
     int p, n, m, s, group_size, rule, max_chunks;
     int no_refresh;  // 1: pass 2 only forms d' (the error pass refreshes X)
+    int chunk;       // users per chunk (chunk_users, at most kChunk)
 };
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
 

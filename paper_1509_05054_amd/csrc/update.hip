@@ -60,8 +60,8 @@ __device__ inline void pass1_body(const UpdateArgs &a, int a0, int a1, int blk, 
     for (int c = blk; c < nch; c += nblk) {
         const int gc = cbase + c;
         const int j = chunk_atom(a.chunk_ptr, a0, a1, gc);
-        const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * kChunk;
-        const int cnt = min(kChunk, a.row_ptr[j + 1] - u0);
+        const int u0 = a.row_ptr[j] + (gc - a.chunk_ptr[j]) * a.chunk;
+        const int cnt = min(a.chunk, a.row_ptr[j + 1] - u0);
         for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
             const int2 ue = a.uent[u0 + r];
             sPos[r] = ue.x;
@@ -227,8 +227,8 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
         const int c0 = a.chunk_ptr[j], c1 = a.chunk_ptr[j + 1];
         if (a.no_refresh && gc != c0)
             continue;  // only the atom's first chunk forms d' (uniform branch)
-        const int u0 = a.row_ptr[j] + (gc - c0) * kChunk;
-        const int cnt = min(kChunk, a.row_ptr[j + 1] - u0);
+        const int u0 = a.row_ptr[j] + (gc - c0) * a.chunk;
+        const int cnt = min(a.chunk, a.row_ptr[j + 1] - u0);
         // g_j = sum of the atom's chunk partials, in chunk order
         float g = 0.f;
         if (t < p)
@@ -537,10 +537,13 @@ int rmse_blocks(int m) { return rmse_blocks_dev(m); }
 // each stride over many blocks and form a tail behind the product tiles.
 bool error_defer_ok(int m) { return m <= 16384; }
 
+int chunk_users(const dl_params &prm) { return prm.group_size >= prm.n ? kChunk : kChunk / 2; }
+
 int max_chunks(const dl_params &prm)
 {
     const long long ms = (long long)prm.m * prm.s;
-    return (int)((ms + kChunk - 1) / kChunk) + prm.n;
+    const int ch = chunk_users(prm);
+    return (int)((ms + ch - 1) / ch) + prm.n;
 }
 
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
@@ -552,7 +555,7 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
         const long long users_ub = (long long)a.m * (a1 - a0) < (long long)a.m * a.s
                                        ? (long long)a.m * (a1 - a0)
                                        : (long long)a.m * a.s;
-        long long chunks_ub = (users_ub + kChunk - 1) / kChunk + (a1 - a0);
+        long long chunks_ub = (users_ub + a.chunk - 1) / a.chunk + (a1 - a0);
         if (chunks_ub > a.max_chunks)
             chunks_ub = a.max_chunks;
         const unsigned grid = (unsigned)(chunks_ub > 2048 ? 2048 : (chunks_ub < 1 ? 1 : chunks_ub));
