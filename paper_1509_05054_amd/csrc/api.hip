@@ -39,7 +39,10 @@ Layout layout_for(const dl_params &prm)
     L.chunk_ptr = take(sizeof(int32_t) * (n + 1));
     L.uent = take(sizeof(int2) * m * s);
     L.atom_state = take(sizeof(int32_t) * n);
-    L.partial = take(sizeof(float) * (size_t)max_chunks(prm) * p);
+    const size_t nsb = (size_t)gsum_signal_blocks(prm);
+    const size_t chunks = (size_t)max_chunks(prm);
+    L.partial = take(sizeof(float) * (chunks > n * nsb ? chunks : n * nsb) * p);
+    L.bcnt = take(sizeof(int32_t) * (nsb ? n * nsb : 1));
     L.rmse_part = take(sizeof(double) * (size_t)rmse_blocks(prm.m));
     if (prm.rule == DL_RULE_NSGK || error_carried(prm)) {
         L.idx_prev = take(sizeof(int32_t) * m * s);
@@ -227,7 +230,8 @@ dl_status run_omp(const dl_params &prm, const float *D, const float *Y, int32_t 
 }
 
 // prev_err: optional error whose partials are complete; its final sum is
-// carried by the scan launch.
+// carried by the scan launch (by pass 1's launch when no user lists are
+// built).
 // The users are written as positions (users) or as (position, val there)
 // pairs (uent); either may be null.
 dl_status run_csr(const dl_params &prm, const int32_t *idx, int32_t *row_ptr, int32_t *users,
@@ -265,9 +269,15 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
 {
     int32_t *row_ptr = ws.at<int32_t>(ws.L.row_ptr);
     int2 *uent = ws.at<int2>(ws.L.uent);
-    dl_status rc = run_csr(prm, idx, row_ptr, nullptr, uent, val, valn, ws, st, prev_err);
-    if (rc != DL_OK)
-        return rc;
+    // pass 1 by signal blocks needs no user lists; pass 2 needs them only to
+    // refresh X itself
+    const int sig_block = gsum_block(prm);
+    const bool lists = !(sig_block && error_refreshes);
+    if (lists) {
+        dl_status rc = run_csr(prm, idx, row_ptr, nullptr, uent, val, valn, ws, st, prev_err);
+        if (rc != DL_OK)
+            return rc;
+    }
     UpdateArgs u;
     u.Y = Y;
     u.D = D;
@@ -291,7 +301,10 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
     u.max_chunks = max_chunks(prm);
     u.no_refresh = error_refreshes ? 1 : 0;
     u.chunk = chunk_users(prm);
-    DL_TRY(launch_update(u, st));
+    u.sig_block = sig_block;
+    u.nsb = gsum_signal_blocks(prm);
+    u.bcnt = ws.at<int32_t>(ws.L.bcnt);
+    DL_TRY(launch_update(u, st, lists ? nullptr : prev_err));
     return DL_OK;
 }
 

@@ -187,9 +187,9 @@ BatchLayout batch_layout(const dl_problem *probs, int count)
     L.upd = take(sizeof(UpdateArgs) * 2 * c);
     L.rmse = take(sizeof(RmseArgs) * 2 * c);
     L.norm = take(sizeof(NormArgs) * c);
-    // 7 stage lists of count + 1 entries, and at most count shape lists of
+    // 8 stage lists of count + 1 entries, and at most count shape lists of
     // (problems in the shape + 1) entries
-    L.lists_len = (int)(8 * (c + 1) + 2 * c);
+    L.lists_len = (int)(9 * (c + 1) + 2 * c);
     L.lists = take(sizeof(int32_t) * (size_t)L.lists_len);
     L.probs_begin = off;
     L.prob.resize(c);
@@ -209,8 +209,8 @@ struct Plan {
     std::vector<NormArgs> norm;   // [count]
     std::vector<int32_t> lists;
     // per stage: offset of its list in `lists` and its item total
-    int l_gemm, l_count, l_quad, l_scatter, l_chunk, l_rmse, l_one;
-    int n_gemm, n_count, n_quad, n_scatter, n_chunk, n_rmse, n_one;
+    int l_gemm, l_count, l_quad, l_scatter, l_pass1, l_chunk, l_rmse, l_one;
+    int n_gemm, n_count, n_quad, n_scatter, n_pass1, n_chunk, n_rmse, n_one;
     struct Shape {
         OmpShape sh;
         int first, num;  // problems [first, first + num) of the OMP table
@@ -243,7 +243,7 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
     P.norm.resize(count);
     P.max_n = 0;
     std::vector<int> it_gemm(count), it_count(count), it_quad(count), it_scatter(count),
-        it_chunk(count), it_rmse(count);
+        it_pass1(count), it_chunk(count), it_rmse(count);
     for (int r = 0; r < count; ++r) {
         const int b = order[r];
         const dl_problem &pb = probs[b];
@@ -285,6 +285,9 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
             u.rule = q.rule;
             u.max_chunks = max_chunks(q);
             u.chunk = chunk_users(q);
+            u.sig_block = gsum_block(q);
+            u.nsb = gsum_signal_blocks(q);
+            u.bcnt = i32(W.bcnt);
             P.upd[par * count + r] = u;
             RmseArgs rm;
             rm.Y = pb.Y;
@@ -323,6 +326,7 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
         it_quad[r] = (q.n + 3) / 4;
         it_scatter[r] = (int)(((long long)q.m * q.s + 255) / 256);
         it_chunk[r] = max_chunks(q);
+        it_pass1[r] = gsum_block(q) ? gsum_items(q) : it_chunk[r];
         it_rmse[r] = rmse_blocks(q.m);
         P.max_n = std::max(P.max_n, q.n);
     }
@@ -341,6 +345,7 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
     add_list(it_count, P.l_count, P.n_count);
     add_list(it_quad, P.l_quad, P.n_quad);
     add_list(it_scatter, P.l_scatter, P.n_scatter);
+    add_list(it_pass1, P.l_pass1, P.n_pass1);
     add_list(it_chunk, P.l_chunk, P.n_chunk);
     add_list(it_rmse, P.l_rmse, P.n_rmse);
     add_list(std::vector<int>(count, 1), P.l_one, P.n_one);
@@ -478,7 +483,8 @@ dl_status iterate_shared(const dl_problem *probs, const std::vector<int> &shared
         DL_TRY(launch_batched_csr(csr, list(P.l_count, count), P.n_count, list(P.l_quad, count),
                                   P.n_quad, list(P.l_scatter, count), P.n_scatter, P.max_n, st,
                                   prev, list(P.l_one, count), k - 1));
-        DL_TRY(launch_batched_update(upd + par, list(P.l_chunk, count), P.n_chunk, st));
+        DL_TRY(launch_batched_update(upd + par, list(P.l_pass1, count), P.n_pass1,
+                                     list(P.l_chunk, count), P.n_chunk, st));
     }
     if (iters > 0)
         DL_TRY(launch_batched_rmse(rmse + (size_t)((iters - 1) & 1) * c, list(P.l_rmse, count),

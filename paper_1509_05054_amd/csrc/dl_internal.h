@@ -20,6 +20,13 @@ constexpr int kCsrBlock = 256;
 // the product launches that carry it, and cost the 128-row GEMM tiles a
 // workgroup per CU).
 constexpr int kRmseSignals = 32;
+// Pass 1 by signal blocks (all atoms in one group): the entries (signals x
+// slots) of one signal block are ranked in LDS, at most this many (a
+// multiple of 256, below 2^13).
+constexpr int kGsumPool = 7168;
+// Signal blocks aimed at by pass 1 by signal blocks (the blocks are made no
+// larger than the pool allows).
+constexpr int kGsumBlocks = 64;
 
 // Device-side counters and control words at the start of the workspace.
 struct Control {
@@ -49,7 +56,8 @@ struct Layout {
     size_t chunk_ptr;  // [n+1] int
     size_t uent;       // [m*s] int2: (ELL position, coefficient bits) of every user, in user order
     size_t atom_state; // [n] int: 0 updated, 1 no users, 2 zero F x^T
-    size_t partial;    // [max_chunks][p] float
+    size_t partial;    // [max(max_chunks, n * nsb)][p] float
+    size_t bcnt;       // [n][nsb] int: users per (atom, signal block) of pass 1 by signal blocks
     size_t rmse_part;  // [rmse_blocks(m)] double
     size_t idx_prev;   // [m][s] int, previous coding (NSGK rule, or a carried error)
     size_t val_prev;   // [m][s] float, previous coding (NSGK rule, or a carried error)
@@ -69,6 +77,16 @@ int max_chunks(const dl_params &prm);
 // group the larger chunks stay faster, 282 vs 279 M, and at m = 262144
 // 483 vs 468 M).
 int chunk_users(const dl_params &prm);
+// Signals per block of pass 1 by signal blocks, or 0 when pass 1 goes over
+// chunks of each atom's user list.  Used with all atoms in one group, when an
+// item's atom range (one atom per lane group of a workgroup) covers at least
+// a thirty-second of the atoms: each item then ranks its block's entries for
+// its own atoms without a global user list.
+int gsum_block(const dl_params &prm);
+// Signal blocks of that pass (0 when it is not used).
+int gsum_signal_blocks(const dl_params &prm);
+// Work items of that pass: (signal block, atom range) pairs.
+int gsum_items(const dl_params &prm);
 int rmse_blocks(int m);
 
 // Optional per-kernel timing (dl_profile_enable): bracket a launch.
@@ -170,8 +188,16 @@ struct UpdateArgs {
     int p, n, m, s, group_size, rule, max_chunks;
     int no_refresh;  // 1: pass 2 only forms d' (the error pass refreshes X)
     int chunk;       // users per chunk (chunk_users, at most kChunk)
+    // pass 1 by signal blocks (gsum_block): signals per block, or 0 for pass 1
+    // over chunks of users; nsb blocks; bcnt [n][nsb] users per (atom, block),
+    // partial [n][nsb][p] the block sums
+    int sig_block, nsb;
+    int32_t *bcnt;
 };
-hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
+// err: optional error whose partials are complete; with pass 1 by signal
+// blocks and no refresh in pass 2 (no user lists built) its final sum runs
+// as one extra workgroup of pass 1's launch.
+hipError_t launch_update(const UpdateArgs &a, hipStream_t st, const RmseArgs *err = nullptr);
 
 struct RmseArgs {
     const float *Y, *D;
@@ -395,8 +421,9 @@ hipError_t launch_batched_csr(const CsrArgs *tab, const BatchList &count_list, i
                               const BatchList &scatter_list, int scatter_items, int max_n,
                               hipStream_t st, const RmseArgs *etab = nullptr,
                               const BatchList &el = BatchList{}, int k = 0);
-hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
-                                 int chunk_items, hipStream_t st);
+hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &pass1_list,
+                                 int pass1_items, const BatchList &chunk_list, int chunk_items,
+                                 hipStream_t st);
 hipError_t launch_batched_rmse(const RmseArgs *tab, const BatchList &bl, int items,
                                const BatchList &final_list, int k, hipStream_t st);
 hipError_t launch_batched_normalize(const NormArgs *tab, const BatchList &bl, int items,

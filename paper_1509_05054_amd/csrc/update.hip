@@ -111,6 +111,212 @@ __global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1
     pass1_body(a, a0, a1, blockIdx.x, gridDim.x);
 }
 
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- pass 1 by signal blocks (all atoms in one group) ---------------------
+// Item (signal block b, atom range r): the range holds one atom per lane
+// group of the workgroup (256 / LPU atoms).  The block's entries (signal,
+// slot) are split over the four waves in contiguous runs, loaded into
+// registers at once.  Each wave counts its entries of the range's atoms per
+// atom, and compacts them, in order, into its own run of an LDS list (ballot
+// and bit count); the counts give every (atom, wave) pair a place in the
+// atoms' lists, and each wave ranks its compacted entries in order (LDS bit
+// masks per atom, as in the CSR count) and writes them there, so every
+// atom's list holds its users of the block in (signal, slot) order.  Each
+// lane group then sums g_jb = sum (e_i + d_j x_ji) x_ji over its atom's list
+// in that order, with the residual rows of U users per lane loaded before
+// any is used, and stores g_jb and the block's user count.  Pass 2 sums an
+// atom's block sums in block order.  Items are numbered so that the ranges
+// of one signal block share a blockIdx residue mod 8: they run on one XCD,
+// whose L2 then serves the block's entries and residual rows to all of them.
+__device__ inline void gsum_item(int it, int nr, int nsb, int &b, int &r)
+{
+    const int g = it / (8 * nr), w = it - g * 8 * nr;
+    const int nl = min(8, nsb - 8 * g);  // blocks in this group of eight
+    b = 8 * g + w % nl;
+    r = w / nl;
+}
+
+constexpr int kGsumRows = 8;  // residual rows in flight per lane
+
+__device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, int nblk)
+{
+    __shared__ unsigned short pool[kGsumPool];  // the atoms' lists (entries of the block)
+    __shared__ unsigned short ce[kGsumPool];    // each wave's entries of the range's atoms
+    __shared__ unsigned char ck[kGsumPool];     // and their atoms within the range
+    __shared__ int wcnt[4][64];
+    __shared__ unsigned long long wmask[4][64];
+    __shared__ int seg0[64], segn[64];
+    __shared__ int wbase[4];
+    const int p = a.p, s = a.s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lpu = lanes_per_user(p);
+    const int R = 256 / lpu;  // atoms per range (at most 64: p >= 16)
+    const int nr = (a1 - a0 + R - 1) / R;
+    const int B = a.sig_block, nsb = a.nsb;
+    const int grp = threadIdx.x / lpu;  // atom of this lane group within the range
+    const int q = 4 * (lane % lpu);
+    const unsigned long long bit = 1ull << lane;
+    const unsigned long long lower = bit - 1ull;
+    // signal of entry e: floor((e + 1/2) / s) in FP32 is exact for entries
+    // below 2^13 (an error under 1e-3 against a distance of at least 1/(2s)
+    // from the next integer)
+    const float inv_s = 1.0f / (float)s;
+    for (int it = blk; it < nr * nsb; it += nblk) {
+        int b, r;
+        gsum_item(it, nr, nsb, b, r);
+        const int lo = a0 + r * R;
+        const int rr = min(R, a1 - lo);
+        const int i0 = b * B;
+        const int len = (min(a.m, i0 + B) - i0) * s;
+        const size_t e0 = (size_t)i0 * s;
+        const int per = ((len + 255) / 256) * 64;  // entries per wave
+        const int w0 = min(len, wave * per), w1 = min(len, w0 + per);
+        // this lane's entries w0 + lane + 64 c, as atoms of the range (-1:
+        // another atom or an unused slot), all loaded before any is used
+        constexpr int kPer = kGsumPool / 256;
+        int kk[kPer];
+#pragma unroll
+        for (int c = 0; c < kPer; ++c) {
+            const int e = w0 + lane + 64 * c;
+            int k = -1;
+            if (e < w1) {
+                k = a.idx[e0 + e] - lo;
+                if ((unsigned)k >= (unsigned)rr)
+                    k = -1;
+            }
+            kk[c] = k;
+        }
+        __syncthreads();  // the previous item's lists are no longer read
+        for (int t = threadIdx.x; t < 4 * 64; t += blockDim.x) {
+            (&wcnt[0][0])[t] = 0;
+            (&wmask[0][0])[t] = 0ull;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kPer; ++c)
+            if (kk[c] >= 0)
+                atomicAdd(&wcnt[wave][kk[c]], 1);
+        __syncthreads();
+        if (wave == 0) {
+            const int v0 = lane < rr ? wcnt[0][lane] : 0;
+            const int v1 = lane < rr ? wcnt[1][lane] : 0;
+            const int v2 = lane < rr ? wcnt[2][lane] : 0;
+            const int v3 = lane < rr ? wcnt[3][lane] : 0;
+            const int tot = v0 + v1 + v2 + v3;
+            int x = tot;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(x, off);
+                if (lane >= off)
+                    x += y;
+            }
+            const int ex = x - tot;
+            seg0[lane] = ex;
+            segn[lane] = tot;
+            wcnt[0][lane] = ex;
+            wcnt[1][lane] = ex + v0;
+            wcnt[2][lane] = ex + v0 + v1;
+            wcnt[3][lane] = ex + v0 + v1 + v2;
+            // each wave's compacted run starts after the earlier waves' runs
+            int t0 = v0, t1 = v1, t2 = v2;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                t0 += __shfl_xor(t0, off);
+                t1 += __shfl_xor(t1, off);
+                t2 += __shfl_xor(t2, off);
+            }
+            if (lane < 4)
+                wbase[lane] = (lane > 0 ? t0 : 0) + (lane > 1 ? t1 : 0) + (lane > 2 ? t2 : 0);
+        }
+        __syncthreads();
+        // compaction of the wave's entries of the range's atoms, in order
+        const int cb0 = wbase[wave];
+        int cb = cb0;
+#pragma unroll
+        for (int c = 0; c < kPer; ++c) {
+            if (w0 + 64 * c >= w1)
+                break;  // uniform over the wave
+            const unsigned long long m = __ballot(kk[c] >= 0);
+            if (kk[c] >= 0) {
+                const int pos = cb + __popcll(m & lower);
+                ce[pos] = (unsigned short)(w0 + lane + 64 * c);
+                ck[pos] = (unsigned char)kk[c];
+            }
+            cb += __popcll(m);
+        }
+        wave_lds_sync();
+        // ranks among the wave's compacted entries of each atom, in order
+        for (int cbase = cb0; cbase < cb; cbase += 64) {
+            const int ci = cbase + lane;
+            const int k = ci < cb ? (int)ck[ci] : -1;
+            const int e = ci < cb ? (int)ce[ci] : 0;
+            if (k >= 0)
+                atomicOr(&wmask[wave][k], bit);
+            wave_lds_sync();
+            unsigned long long mm = 0;
+            int base = 0;
+            if (k >= 0) {
+                mm = wmask[wave][k];
+                base = wcnt[wave][k];
+                pool[base + __popcll(mm & lower)] = (unsigned short)e;
+            }
+            wave_lds_sync();
+            if (k >= 0 && lane == 63 - __clzll((long long)mm)) {
+                wcnt[wave][k] = base + __popcll(mm);
+                wmask[wave][k] = 0ull;
+            }
+            wave_lds_sync();
+        }
+        __syncthreads();
+        if (grp < rr) {
+            const int j = lo + grp;
+            const int u0 = seg0[grp], cnt = segn[grp];
+            const f32x4 d = load4(a.D + (size_t)j * p, q, p);
+            const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+            f32x4 acc = zero;
+            constexpr int U = kGsumRows;
+            for (int ub = 0; ub < cnt; ub += U) {
+                f32x4 er[U];
+                float x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool on = ub + u < cnt;
+                    const int e = on ? (int)pool[u0 + ub + u] : 0;
+                    const int il = (int)(((float)e + 0.5f) * inv_s);
+                    x[u] = on ? a.val[e0 + e] : 0.f;
+                    er[u] = on ? load4(a.E + (size_t)(i0 + il) * p, q, p) : zero;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ub + u < cnt)
+                        acc += (er[u] + d * x[u]) * x[u];
+            }
+            const size_t row = (size_t)(j - a0) * nsb + b;
+            if (q < p)
+                *reinterpret_cast<f32x4 *>(a.partial + row * p + q) = acc;
+            if (lane % lpu == 0)
+                a.bcnt[row] = cnt;
+        }
+    }
+}
+
+// The optional last workgroup sums a carried error's partials.
+__global__ __launch_bounds__(256) void gsum_kernel(UpdateArgs a, int a0, int a1, RmseArgs err,
+                                                   int eb)
+{
+    if (eb > 0 && blockIdx.x == gridDim.x - 1) {
+        rmse_final_body(err, eb);
+        return;
+    }
+    gsum_body(a, a0, a1, blockIdx.x, gridDim.x - (eb > 0 ? 1 : 0));
+}
+
 // ---- pass 2: d_j' and the AK-SVD representation refresh ------------------
 // Every chunk of atom j sums the atom's chunk partials in chunk order (so
 // every chunk gets the same bits), normalises (d_j' = g_j / ||g_j||, eq. 5
@@ -128,6 +334,38 @@ __device__ inline float block_sum_f32(float v, float *red4)
         red4[threadIdx.x >> 6] = v;
     __syncthreads();
     return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
+// g_j, coordinate t < p: the atom's partials summed in order, those of its
+// user chunks [c0, c1) or, with pass 1 by signal blocks, its block sums.
+__device__ inline float atom_g(const UpdateArgs &a, int j, int a0, int c0, int c1, int t)
+{
+    const int p = a.p;
+    if (t >= p)
+        return 0.f;
+    const float *src;
+    int cnt;
+    if (a.sig_block) {
+        src = a.partial + (size_t)(j - a0) * a.nsb * p + t;
+        cnt = a.nsb;
+    } else {
+        src = a.partial + (size_t)c0 * p + t;
+        cnt = c1 - c0;
+    }
+    float g = 0.f;
+    int c = 0;
+    for (; c + 8 <= cnt; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = src[(size_t)(c + u) * p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            g += v[u];
+    }
+    for (; c < cnt; ++c)
+        g += src[(size_t)c * p];
+    return g;
 }
 
 // x' = (e + d x)^T d' for the chunk's users staged in sPos/sX; every lane of
@@ -189,7 +427,16 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
         // blk + nblk, ... of the group, each summing its chunk partials in
         // chunk order; atoms without users keep d_j
         for (int j = a0 + blk; j < a1; j += nblk) {
-            const int c0 = a.chunk_ptr[j], c1 = a.chunk_ptr[j + 1];
+            int c0 = 0, c1 = 0;
+            if (a.sig_block) {  // users counted per signal block
+                int used = 0;
+                for (int bb = t; bb < a.nsb; bb += blockDim.x)
+                    used |= a.bcnt[(size_t)(j - a0) * a.nsb + bb];
+                c1 = __syncthreads_or(used) ? 1 : 0;
+            } else {
+                c0 = a.chunk_ptr[j];
+                c1 = a.chunk_ptr[j + 1];
+            }
             if (c0 == c1) {  // uniform
                 for (int k = t; k < p; k += blockDim.x)
                     a.Dn[(size_t)j * p + k] = a.D[(size_t)j * p + k];
@@ -199,10 +446,7 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
                 }
                 continue;
             }
-            float g = 0.f;
-            if (t < p)
-                for (int cc = c0; cc < c1; ++cc)
-                    g += a.partial[(size_t)cc * p + t];
+            const float g = atom_g(a, j, a0, c0, c1, t);
             const float sq = block_sum_f32(g * g, red4);
             const int state = sq > 0.f ? 0 : 2;
             const float inv = state == 0 ? 1.0f / sqrtf(sq) : 0.f;
@@ -229,11 +473,7 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
             continue;  // only the atom's first chunk forms d' (uniform branch)
         const int u0 = a.row_ptr[j] + (gc - c0) * a.chunk;
         const int cnt = min(a.chunk, a.row_ptr[j + 1] - u0);
-        // g_j = sum of the atom's chunk partials, in chunk order
-        float g = 0.f;
-        if (t < p)
-            for (int cc = c0; cc < c1; ++cc)
-                g += a.partial[(size_t)cc * p + t];
+        const float g = atom_g(a, j, a0, c0, c1, t);
         const float sq = block_sum_f32(g * g, red4);
         const int state = sq > 0.f ? 0 : 2;  // 2: F x^T = 0 (or not finite): unchanged
         const float inv = state == 0 ? 1.0f / sqrtf(sq) : 0.f;
@@ -424,7 +664,8 @@ __global__ __launch_bounds__(256) void normalize_kernel(float *D, int n, int p, 
 }
 
 // ---- batched problems (one group per problem: atoms [0, n)) --------------
-// Items: pass 1 and pass 2 = chunk slots (an upper bound of the chunks; the
+// Items: pass 1 = chunk slots, or (signal block, atom range) pairs with pass
+// 1 by signal blocks; pass 2 = chunk slots (an upper bound of the chunks; the
 // excess leaves at once, and pass 2's slots also cover the atom quads of its
 // unused-atom step), error = signal blocks,
 // normalisation = atom quads.
@@ -441,9 +682,12 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restri
         if (batch_owner(bl.start, bl.count, cur.it, own))
             a = tab[own.b];
         const int t = cur.it - own.b0, nt = own.b1 - own.b0;
-        if (STAGE == 0)
-            pass1_body(a, 0, a.n, t, nt);
-        else
+        if (STAGE == 0) {
+            if (a.sig_block)
+                gsum_body(a, 0, a.n, t, nt);
+            else
+                pass1_body(a, 0, a.n, t, nt);
+        } else
             pass2_body<4>(a, 0, a.n, t, nt);
     }
     if (threadIdx.x == 0)
@@ -546,7 +790,41 @@ int max_chunks(const dl_params &prm)
     return (int)((ms + ch - 1) / ch) + prm.n;
 }
 
-hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
+static int host_lanes_per_user(int p)
+{
+    int l = 1;
+    while (4 * l < p)
+        l <<= 1;
+    return l;
+}
+
+int gsum_block(const dl_params &prm)
+{
+    if (prm.group_size < prm.n || prm.p < 16)
+        return 0;
+    const int R = 256 / host_lanes_per_user(prm.p);
+    if ((prm.n + R - 1) / R > 32)
+        return 0;
+    // about kGsumBlocks blocks, in multiples of 64 signals, within the pool
+    int B = (prm.m + kGsumBlocks - 1) / kGsumBlocks;
+    B = (B + 63) / 64 * 64;
+    const int cap = kGsumPool / prm.s / 64 * 64;
+    return B < cap ? B : cap;
+}
+
+int gsum_signal_blocks(const dl_params &prm)
+{
+    const int B = gsum_block(prm);
+    return B ? (prm.m + B - 1) / B : 0;
+}
+
+int gsum_items(const dl_params &prm)
+{
+    const int R = 256 / host_lanes_per_user(prm.p);
+    return gsum_signal_blocks(prm) * ((prm.n + R - 1) / R);
+}
+
+hipError_t launch_update(const UpdateArgs &a, hipStream_t st, const RmseArgs *err)
 {
     const int gs = a.group_size >= a.n ? a.n : a.group_size;
     for (int a0 = 0; a0 < a.n; a0 += gs) {
@@ -560,7 +838,18 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
             chunks_ub = a.max_chunks;
         const unsigned grid = (unsigned)(chunks_ub > 2048 ? 2048 : (chunks_ub < 1 ? 1 : chunks_ub));
         prof_begin(DL_K_UPD_PASS1, st);
-        hipLaunchKernelGGL(pass1_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
+        if (a.sig_block) {
+            // one group (a0 = 0, a1 = n); at most 4096 workgroups, a multiple
+            // of 8 when the items are more, so an item keeps its XCD
+            const int R = 256 / host_lanes_per_user(a.p);
+            const int items = a.nsb * ((a1 - a0 + R - 1) / R);
+            const int g1 = items < 4096 ? items : 4096;
+            const int eb = err ? rmse_blocks_dev(err->m) : 0;
+            hipLaunchKernelGGL(gsum_kernel, dim3(g1 + (err ? 1 : 0)), dim3(256), 0, st, a, a0, a1,
+                               err ? *err : RmseArgs{}, eb);
+        } else {
+            hipLaunchKernelGGL(pass1_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
+        }
         prof_end(DL_K_UPD_PASS1, st);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
@@ -590,13 +879,14 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
     return hipSuccess;
 }
 
-hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &chunk_list,
-                                 int chunk_items, hipStream_t st)
+hipError_t launch_batched_update(const UpdateArgs *tab, const BatchList &pass1_list,
+                                 int pass1_items, const BatchList &chunk_list, int chunk_items,
+                                 hipStream_t st)
 {
-    int wg = batch_workers((const void *)update_batched<0>, 256, 0, chunk_items);
+    int wg = batch_workers((const void *)update_batched<0>, 256, 0, pass1_items);
     prof_begin(DL_K_UPD_PASS1, st);
-    hipLaunchKernelGGL(update_batched<0>, dim3(wg), dim3(256), 0, st, tab, chunk_list,
-                       batch_per_ticket(chunk_items, wg));
+    hipLaunchKernelGGL(update_batched<0>, dim3(wg), dim3(256), 0, st, tab, pass1_list,
+                       batch_per_ticket(pass1_items, wg));
     prof_end(DL_K_UPD_PASS1, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
