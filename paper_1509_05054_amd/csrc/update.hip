@@ -336,22 +336,9 @@ __device__ inline float block_sum_f32(float v, float *red4)
     return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
-// g_j, coordinate t < p: the atom's partials summed in order, those of its
-// user chunks [c0, c1) or, with pass 1 by signal blocks, its block sums.
-__device__ inline float atom_g(const UpdateArgs &a, int j, int a0, int c0, int c1, int t)
+// Sum of cnt rows (stride p) from src, in row order, loads eight at a time.
+__device__ inline float sum_rows(const float *src, int cnt, int p)
 {
-    const int p = a.p;
-    if (t >= p)
-        return 0.f;
-    const float *src;
-    int cnt;
-    if (a.sig_block) {
-        src = a.partial + (size_t)(j - a0) * a.nsb * p + t;
-        cnt = a.nsb;
-    } else {
-        src = a.partial + (size_t)c0 * p + t;
-        cnt = c1 - c0;
-    }
     float g = 0.f;
     int c = 0;
     for (; c + 8 <= cnt; c += 8) {
@@ -366,6 +353,37 @@ __device__ inline float atom_g(const UpdateArgs &a, int j, int a0, int c0, int c
     for (; c < cnt; ++c)
         g += src[(size_t)c * p];
     return g;
+}
+
+// g_j, coordinate t = threadIdx.x < p (workgroup-wide: every thread calls
+// it): the atom's partials summed in order, those of its user chunks
+// [c0, c1), or, with pass 1 by signal blocks, its block sums: the workgroup
+// splits them into W contiguous runs (W = 256 / P, P the power of two >= p),
+// sums each run in block order, and adds the run sums in run order.
+__device__ inline float atom_g(const UpdateArgs &a, int j, int a0, int c0, int c1, int t)
+{
+    const int p = a.p;
+    if (!a.sig_block)
+        return t < p ? sum_rows(a.partial + (size_t)c0 * p + t, c1 - c0, p) : 0.f;
+    __shared__ float sg[256];
+    int P = 1;
+    while (P < p)
+        P <<= 1;
+    const int W = 256 / P;
+    const int tc = threadIdx.x % P, part = threadIdx.x / P;
+    const int per = (a.nsb + W - 1) / W;
+    const int b0 = min(a.nsb, part * per), b1 = min(a.nsb, b0 + per);
+    const float g = tc < p ? sum_rows(a.partial + ((size_t)(j - a0) * a.nsb + b0) * p + tc,
+                                      b1 - b0, p)
+                           : 0.f;
+    __syncthreads();  // sg of the previous atom is no longer read
+    sg[threadIdx.x] = g;
+    __syncthreads();
+    float r = 0.f;
+    if (t < p)
+        for (int w = 0; w < W; ++w)
+            r += sg[w * P + t];
+    return r;
 }
 
 // x' = (e + d x)^T d' for the chunk's users staged in sPos/sX; every lane of
