@@ -283,6 +283,46 @@ def test_update_unused_and_zero_atoms(gs):
     assert (np.abs(vng - vnr) / ynorm).max() < 1e-4
 
 
+# With all atoms in one group, pass 1 goes by signal blocks for these shapes
+# (one atom per lane group of an item, at most 32 atom ranges): ragged last
+# signal block and atom range, trailing unused slots (-1, 0), one atom used by
+# every signal, a single signal block, the largest s (the smallest blocks),
+# and more items than the launch has workgroups.
+GSUM_CASES = [
+    ("p36 n72 ragged range and block", 36, 72, 5, 1001),
+    ("p20 n50 two ranges", 20, 50, 4, 1500),
+    ("p64 m37 one block", 64, 128, 3, 37),
+    ("p144 n128 four-atom ranges", 144, 128, 8, 2500),
+    ("p16 n1024 s16 items over the grid", 16, 1024, 16, 120000),
+]
+
+
+@pytest.mark.parametrize("name,p,n,s,m", GSUM_CASES, ids=[c[0] for c in GSUM_CASES])
+def test_update_by_signal_blocks_edge_cases(name, p, n, s, m):
+    note(f"update by signal blocks {name}")
+    rng = np.random.default_rng(1000 * p + n + m)
+    D = rng.standard_normal((n, p))
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    Y = rng.standard_normal((m, p)).astype(np.float32)
+    idx = np.empty((m, s), dtype=np.int32)
+    idx[:, 0] = 0  # atom 0 in every signal
+    for i in range(m):
+        idx[i, 1:] = 1 + rng.choice(n - 1, size=s - 1, replace=False)
+    val = rng.standard_normal((m, s)).astype(np.float32)
+    if s > 1:  # a tenth of the signals stop early
+        for i in np.flatnonzero(rng.random(m) < 0.1):
+            cut = int(rng.integers(1, s))
+            idx[i, cut:] = -1
+            val[i, cut:] = 0.0
+    Dr, vnr, unused = oracle.jau_update(Y, D, idx, val, n)
+    Dg, vng, st = gpu_update(Y, D, idx, val, n)
+    assert st["unused_atoms"] == unused
+    assert np.abs(Dg - Dr).max() < 1e-4, np.abs(Dg - Dr).max()
+    ynorm = np.linalg.norm(Y.astype(np.float64), axis=1, keepdims=True)
+    assert (np.abs(vng - vnr) / ynorm).max() < 1e-4
+    np.testing.assert_array_equal(vng[idx < 0], 0.0)
+
+
 def test_update_sgk_rule_keeps_x_and_matches_aksvd_atoms():
     note("update sgk")
     Y, D = _patch_problem(64, 128, 4000, seed=5)
