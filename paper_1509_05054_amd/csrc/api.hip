@@ -39,6 +39,7 @@ Layout layout_for(const dl_params &prm)
     L.chunk_ptr = take(sizeof(int32_t) * (n + 1));
     L.uent = take(sizeof(int2) * m * s);
     L.atom_state = take(sizeof(int32_t) * n);
+    L.atom_cos = take(sizeof(float) * n);
     const size_t nsb = (size_t)gsum_signal_blocks(prm);
     const size_t chunks = (size_t)max_chunks(prm);
     L.partial = take(sizeof(float) * (chunks > n * nsb ? chunks : n * nsb) * p);
@@ -144,7 +145,7 @@ dl_status products(const dl_params &prm, const float *D, const float *Y, float *
                    const Ws *ws, hipStream_t st, int ldn, const int32_t *m_dev = nullptr,
                    const RmseArgs *prev_err = nullptr, float *Gdiag = nullptr)
 {
-    if (prev_err && (!(G && A0) || !prev_err->Dold))
+    if (prev_err && (!(G && A0) || !prev_err->refresh))
         return DL_EINVAL;  // the launch carries only the refreshing error pass
     if (prm.precision == DL_PREC_BF16) {
         uint16_t *Dbf = ws->at<uint16_t>(ws->L.Dbf);
@@ -290,6 +291,7 @@ dl_status run_update(const dl_params &prm, const float *Y, const float *D, float
     u.chunk_ptr = ws.at<int32_t>(ws.L.chunk_ptr);
     u.uent = uent;
     u.atom_state = ws.at<int32_t>(ws.L.atom_state);
+    u.atom_cos = ws.at<float>(ws.L.atom_cos);
     u.partial = ws.at<float>(ws.L.partial);
     u.ctl = ws.ctl();
     u.p = prm.p;
@@ -327,15 +329,16 @@ RmseArgs rmse_args(const dl_params &prm, const float *Y, const float *D, const i
 }
 
 // The error pass also forms the refreshed coefficients valn from the
-// coefficients val_old, the residual E and the dictionary Dold the coding
-// used (all atoms in one group, after an update with error_refreshes).
-void add_refresh(RmseArgs &r, const dl_params &prm, const float *Dold, const float *val_old,
-                 float *valn, const Ws &ws, const float *E = nullptr)
+// coefficients val_old, the residual E and pass 2's d^T d' per atom (all
+// atoms in one group, after an update with error_refreshes).
+void add_refresh(RmseArgs &r, const dl_params &prm, const float *val_old, float *valn,
+                 const Ws &ws, const float *E = nullptr)
 {
-    r.Dold = Dold;
+    r.refresh = 1;
     r.E = E ? E : ws.at<float>(ws.L.E);
     r.val_old = val_old;
     r.atom_state = ws.at<int32_t>(ws.L.atom_state);
+    r.atom_cos = ws.at<float>(ws.L.atom_cos);
     r.valn = valn;
     r.rule = prm.rule;
 }
@@ -618,7 +621,7 @@ static dl_status iterate_impl(const dl_params *prm, const float *Y, float *D, in
         float *xout = nsgk ? val_k : X_val;
         prev = rmse_args(q, Y, Dnext, idx_k, xout, rmse + k, w);
         if (one_group)
-            add_refresh(prev, q, Dcur, val_k, xout, w, E_k);
+            add_refresh(prev, q, val_k, xout, w, E_k);
         pending = defer;
         if (!defer)
             DL_TRY(launch_rmse(prev, st));
@@ -773,7 +776,7 @@ dl_status dl_iterate_proposed(const dl_params *prm, const dl_proposal *pr, const
             return rc;
         RmseArgs ra = rmse_args(q, Y, Dnext, X_idx, X_val, rmse + k, w);
         if (one_group)
-            add_refresh(ra, q, Dcur, val_ws, X_val, w);
+            add_refresh(ra, q, val_ws, X_val, w);
         DL_TRY(launch_rmse(ra, st));
         float *t = Dcur;
         Dcur = Dnext;

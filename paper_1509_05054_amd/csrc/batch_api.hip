@@ -275,6 +275,7 @@ void build_plan(const dl_problem *probs, const std::vector<int> &members, char *
             u.chunk_ptr = i32(W.chunk_ptr);
             u.uent = reinterpret_cast<const int2 *>(wb + W.uent);
             u.atom_state = i32(W.atom_state);
+            u.atom_cos = f(W.atom_cos);
             u.partial = f(W.partial);
             u.ctl = c;
             u.p = q.p;

@@ -56,6 +56,7 @@ struct Layout {
     size_t chunk_ptr;  // [n+1] int
     size_t uent;       // [m*s] int2: (ELL position, coefficient bits) of every user, in user order
     size_t atom_state; // [n] int: 0 updated, 1 no users, 2 zero F x^T
+    size_t atom_cos;   // [n] float: d_j^T d_j' of the updated atoms
     size_t partial;    // [max(max_chunks, n * nsb)][p] float
     size_t bcnt;       // [n][nsb] int: users per (atom, signal block) of pass 1 by signal blocks
     size_t rmse_part;  // [rmse_blocks(m)] double
@@ -183,6 +184,7 @@ struct UpdateArgs {
     const int32_t *row_ptr, *chunk_ptr;
     const int2 *uent;     // [m*s] (ELL position, val there) of every user, in user order
     int32_t *atom_state;
+    float *atom_cos;      // [n] d_j^T d_j' (the refresh's x term)
     float *partial;
     Control *ctl;
     int p, n, m, s, group_size, rule, max_chunks;
@@ -207,14 +209,17 @@ struct RmseArgs {
     double *out;      // one double
     Control *ctl;
     int p, n, m, s;
-    // Optional refresh (all atoms in one group): with Dold set, the pass also
-    // forms the refreshed coefficients val = (e + d x)^T d' (eq. 5, second
-    // line) from the coefficients val_old, residual E and dictionary Dold
-    // before the update (D is the updated one), writes them to valn, and
-    // measures the error with them.  Atoms whose atom_state is not 0, and the
-    // SGK rule, keep their coefficients.
-    const float *Dold = nullptr, *E = nullptr, *val_old = nullptr;
+    // Optional refresh (all atoms in one group, D the updated dictionary):
+    // with refresh set, the pass also forms the refreshed coefficients
+    // x' = (e + d x)^T d' (eq. 5, second line) as e^T d' + x (d^T d'), from
+    // the coefficients val_old, the residual E and atom_cos = d^T d' per atom
+    // (pass 2's), writes them to valn, and measures the error with them.
+    // Atoms whose atom_state is not 0, and the SGK rule, keep their
+    // coefficients.
+    int refresh = 0;
+    const float *E = nullptr, *val_old = nullptr;
     const int32_t *atom_state = nullptr;
+    const float *atom_cos = nullptr;
     float *valn = nullptr;
     int rule = 0;
 };

@@ -137,17 +137,21 @@ __device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
 }
 
 // The same partials with the coefficient refresh of the atom update (all
-// atoms in one group): per slot, x' = (e + d x)^T d' with the operations and
-// order of pass 2 (so the same bits), stored to valn, and the residual row
+// atoms in one group): per slot, x' = (e + d x)^T d' formed as
+// e^T d' + x (d^T d') with pass 2's operations and order (so the same bits;
+// d^T d' is pass 2's per-atom atom_cos), stored to valn, and the residual row
 // y - sum_t d'_t x'_t formed as above.  Two signals per lane group in flight
-// (each slot needs the old and the new atom row).  Every lane of a group runs
-// the loop (zero rows past p), since x' is reduced over the group.
+// (each slot needs its new atom row).  Every lane of a group runs the loop
+// (zero rows past p), since x' is reduced over the group.
 __device__ inline void rmse_refresh_body(const RmseArgs &a, int blk, int nblk)
 {
     __shared__ double red4[4];
     __shared__ int sIdx[kRmseSignals * 16];
     __shared__ float sVal[kRmseSignals * 16];
-    __shared__ int sKeep[kRmseSignals * 16];
+    // per slot: d^T d' of an atom whose coefficient is refreshed, NaN for a
+    // slot that keeps its coefficient (one array: the carrying launches'
+    // LDS budgets count it)
+    __shared__ float sCos[kRmseSignals * 16];
     const int p = a.p, s = a.s, n = a.n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpu = lanes_per_user(p);
@@ -164,16 +168,16 @@ __device__ inline void rmse_refresh_body(const RmseArgs &a, int blk, int nblk)
         for (int r = threadIdx.x; r < nsig * s; r += blockDim.x) {
             int j = a.idx[(size_t)i0 * s + r];
             float x = a.val_old[(size_t)i0 * s + r];
-            int keep = 1;
+            float cj = __builtin_nanf("");
             if (j < 0 || j >= n) {
                 j = 0;  // unused slot: row 0, coefficient 0 (kept)
                 x = 0.f;
-            } else {
-                keep = a.rule != DL_RULE_AKSVD || a.atom_state[j] != 0;
+            } else if (a.rule == DL_RULE_AKSVD && a.atom_state[j] == 0) {
+                cj = a.atom_cos[j];  // NaN only if d' is not finite: kept then
             }
             sIdx[r] = j;
             sVal[r] = x;
-            sKeep[r] = keep;
+            sCos[r] = cj;
         }
         __syncthreads();
         constexpr int RU = 2;  // measured: 4 in flight was 6% slower at c2
@@ -190,15 +194,14 @@ __device__ inline void rmse_refresh_body(const RmseArgs &a, int blk, int nblk)
                 ey[u] = on[u] ? load4(a.Y + (size_t)(i0 + il) * p, q, p) : zero;
                 eo[u] = on[u] ? load4(a.E + (size_t)(i0 + il) * p, q, p) : zero;
             }
-            // TS slots at a time: all their atom rows (old and new) are
-            // loaded before any is used, so the loads are in flight together
-            // (the stores of x' between them would otherwise order each
-            // slot's loads after the previous slot's store)
+            // TS slots at a time: all their atom rows are loaded before any
+            // is used, so the loads are in flight together (the stores of x'
+            // between them would otherwise order each slot's loads after the
+            // previous slot's store)
             constexpr int TS = 4;
             for (int t0 = 0; t0 < s; t0 += TS) {
-                f32x4 dn[RU][TS], dd[RU][TS];
-                float x[RU][TS];
-                int kp[RU][TS];
+                f32x4 dn[RU][TS];
+                float x[RU][TS], cj[RU][TS];
 #pragma unroll
                 for (int u = 0; u < RU; ++u)
 #pragma unroll
@@ -207,9 +210,8 @@ __device__ inline void rmse_refresh_body(const RmseArgs &a, int blk, int nblk)
                         const int r = ilc[u] * s + t;
                         const int j = sIdx[r];
                         x[u][v] = on[u] ? sVal[r] : 0.f;
-                        kp[u][v] = on[u] ? sKeep[r] : 1;
+                        cj[u][v] = on[u] ? sCos[r] : __builtin_nanf("");
                         dn[u][v] = load4(a.D + (size_t)j * p, q, p);
-                        dd[u][v] = load4(a.Dold + (size_t)j * p, q, p);
                     }
 #pragma unroll
                 for (int v = 0; v < TS; ++v) {
@@ -217,12 +219,12 @@ __device__ inline void rmse_refresh_body(const RmseArgs &a, int blk, int nblk)
                         break;  // uniform over the workgroup
 #pragma unroll
                     for (int u = 0; u < RU; ++u) {
-                        const f32x4 f = eo[u] + dd[u][v] * x[u][v];
-                        float part = f[0] * dn[u][v][0] + f[1] * dn[u][v][1] +
-                                     f[2] * dn[u][v][2] + f[3] * dn[u][v][3];
+                        float part = eo[u][0] * dn[u][v][0] + eo[u][1] * dn[u][v][1] +
+                                     eo[u][2] * dn[u][v][2] + eo[u][3] * dn[u][v][3];
                         for (int off = 1; off < lpu; off <<= 1)
                             part += __shfl_xor(part, off);
-                        const float xn = kp[u][v] ? x[u][v] : part;
+                        const bool keep = cj[u][v] != cj[u][v];  // NaN: kept
+                        const float xn = keep ? x[u][v] : part + x[u][v] * cj[u][v];
                         if (on[u] && (lane % lpu) == 0)
                             a.valn[(size_t)(i0 + ilc[u]) * s + t0 + v] = xn;
                         ey[u] -= dn[u][v] * xn;

@@ -386,12 +386,14 @@ __device__ inline float atom_g(const UpdateArgs &a, int j, int a0, int c0, int c
     return r;
 }
 
-// x' = (e + d x)^T d' for the chunk's users staged in sPos/sX; every lane of
+// x' = (e + d x)^T d', formed as e^T d' + x (d^T d') with cj = d^T d' (the
+// same value with one atom row per user instead of two), for the chunk's
+// users staged in sPos/sX; every lane of
 // the wave runs the same trip count (shuffles below), and the residual rows
 // of U users per lane are loaded before any of them is used, so their loads
 // are in flight together.
 template <int U>
-__device__ inline void pass2_refresh(const UpdateArgs &a, f32x4 d, f32x4 dn, const int *sPos,
+__device__ inline void pass2_refresh(const UpdateArgs &a, float cj, f32x4 dn, const int *sPos,
                                      const float *sX, int cnt, int wave, int lane, int lpu,
                                      int upw, int sub, int q)
 {
@@ -411,12 +413,11 @@ __device__ inline void pass2_refresh(const UpdateArgs &a, f32x4 d, f32x4 dn, con
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const f32x4 f = e[u] + d * x[u];
-            float part = f[0] * dn[0] + f[1] * dn[1] + f[2] * dn[2] + f[3] * dn[3];
+            float part = e[u][0] * dn[0] + e[u][1] * dn[1] + e[u][2] * dn[2] + e[u][3] * dn[3];
             for (int off = 1; off < lpu; off <<= 1)
                 part += __shfl_xor(part, off);
             if (pos[u] >= 0 && (lane % lpu) == 0)
-                a.valn[pos[u]] = part;
+                a.valn[pos[u]] = part + x[u] * cj;
         }
     }
 }
@@ -468,9 +469,13 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
             const float sq = block_sum_f32(g * g, red4);
             const int state = sq > 0.f ? 0 : 2;
             const float inv = state == 0 ? 1.0f / sqrtf(sq) : 0.f;
+            const float dt = t < p ? a.D[(size_t)j * p + t] : 0.f;
+            const float dnt = state == 0 ? g * inv : dt;
             if (t < p)
-                a.Dn[(size_t)j * p + t] = state == 0 ? g * inv : a.D[(size_t)j * p + t];
+                a.Dn[(size_t)j * p + t] = dnt;
+            const float cj = block_sum_f32(dt * dnt, red4);  // d^T d' for the refresh
             if (t == 0) {
+                a.atom_cos[j] = cj;
                 a.atom_state[j] = state;
                 if (state == 2) {
                     atomicAdd(&a.ctl->zero_updates, 1ull);
@@ -495,13 +500,16 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
         const float sq = block_sum_f32(g * g, red4);
         const int state = sq > 0.f ? 0 : 2;  // 2: F x^T = 0 (or not finite): unchanged
         const float inv = state == 0 ? 1.0f / sqrtf(sq) : 0.f;
+        const float dt = t < p ? a.D[(size_t)j * p + t] : 0.f;
+        const float dnt = state == 0 ? g * inv : dt;
         if (t < p) {
-            const float dn = state == 0 ? g * inv : a.D[(size_t)j * p + t];
-            sDn[t] = dn;
+            sDn[t] = dnt;
             if (gc == c0)
-                a.Dn[(size_t)j * p + t] = dn;
+                a.Dn[(size_t)j * p + t] = dnt;
         }
+        const float cj = block_sum_f32(dt * dnt, red4);  // d^T d' for the refresh
         if (gc == c0 && t == 0) {
+            a.atom_cos[j] = cj;
             a.atom_state[j] = state;
             if (state == 2) {
                 atomicAdd(&a.ctl->zero_updates, 1ull);
@@ -511,7 +519,9 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
         }
         if (a.no_refresh)
             continue;  // the error pass refreshes X
-        const bool keep = a.rule != DL_RULE_AKSVD || state != 0;
+        // kept: other rules, atoms not updated, and (as in the error pass's
+        // refresh) a d^T d' that is not a number
+        const bool keep = a.rule != DL_RULE_AKSVD || state != 0 || cj != cj;
         for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
             const int2 ue = a.uent[u0 + r];
             sPos[r] = ue.x;
@@ -522,16 +532,15 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
             for (int r = threadIdx.x; r < cnt; r += blockDim.x)
                 a.valn[sPos[r]] = sX[r];
         } else {
-            const f32x4 d = load4(a.D + (size_t)j * p, q, p);
             const f32x4 dn = q < p ? *reinterpret_cast<const f32x4 *>(sDn + q)
                                    : f32x4{0.f, 0.f, 0.f, 0.f};
             if (U > 0)
-                pass2_refresh<(U > 0 ? U : 4)>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw,
+                pass2_refresh<(U > 0 ? U : 4)>(a, cj, dn, sPos, sX, cnt, wave, lane, lpu, upw,
                                                 sub, q);
             else if (lpu <= 16)
-                pass2_refresh<8>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
+                pass2_refresh<8>(a, cj, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
             else
-                pass2_refresh<4>(a, d, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
+                pass2_refresh<4>(a, cj, dn, sPos, sX, cnt, wave, lane, lpu, upw, sub, q);
         }
         __syncthreads();
     }
@@ -950,7 +959,7 @@ hipError_t launch_rmse(const RmseArgs &a, hipStream_t st)
 {
     const int nb = rmse_blocks(a.m);
     prof_begin(DL_K_RMSE, st);
-    if (a.Dold)
+    if (a.refresh)
         hipLaunchKernelGGL(rmse_kernel<true>, dim3(nb), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(rmse_kernel<false>, dim3(nb), dim3(256), 0, st, a);
