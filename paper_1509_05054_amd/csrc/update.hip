@@ -336,18 +336,18 @@ __device__ inline float block_sum_f32(float v, float *red4)
     return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
-// Sum of cnt rows (stride p) from src, in row order, loads eight at a time.
+// Sum of cnt rows (stride p) from src, in row order, loads sixteen at a time.
 __device__ inline float sum_rows(const float *src, int cnt, int p)
 {
     float g = 0.f;
     int c = 0;
-    for (; c + 8 <= cnt; c += 8) {
-        float v[8];
+    for (; c + 16 <= cnt; c += 16) {
+        float v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 16; ++u)
             v[u] = src[(size_t)(c + u) * p];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 16; ++u)
             g += v[u];
     }
     for (; c < cnt; ++c)
