@@ -88,3 +88,43 @@ def test_bf16_iterate_error_against_fp64_oracle():
     assert rel_emul[0] < 1e-4, rel_emul
     assert rel_emul.max() < 2e-3, rel_emul
     assert rel_exact.max() < 2e-2, rel_exact
+
+
+def test_bf16_precision_workload_full_size_one_iteration():
+    """The precision workload at its full size (65,536 signals, p=256,
+    n=1024, s=12), one iteration teacher-forced: the BF16 coding at D0
+    against the oracle fed the same BF16-rounded D and Y (supports, near-tie
+    validity of every disagreement, coefficients), then the FP32 atom update
+    from the oracle's coding against the FP64 update."""
+    note("bf16 precision workload full size, one iteration")
+    w = synth.workload("patches_p256_n1024_s12_m65536")
+    p, n, m, s = w.p, w.n, w.m, w.s
+    assert m == 65536
+    prm = dl.Params(p, n, m, s, precision=dl.PREC_BF16)
+    ws = dl.workspace(prm)
+    idx = torch.empty((m, s), dtype=torch.int32, device="cuda")
+    val = torch.empty((m, s), device="cuda")
+    dl.omp(prm, dev(w.D0), dev(w.Y), idx, val, ws)
+    ig, vg = host(idx), host(val)
+    Db, Yb = round_bf16(w.D0), round_bf16(w.Y)
+    ir, vr, _ = oracle.omp(Db, Yb, s)
+    agree = support_agreement(ig, ir)
+    print(f"full-size BF16 coding: support agreement {agree:.5f}")
+    assert agree >= 0.995, agree
+    assert not disagreements_are_near_ties(Db, Yb, ig, ir)
+    same = np.all(ig == ir, axis=1)
+    yn = np.linalg.norm(Yb.astype(np.float64), axis=1, keepdims=True)
+    assert (np.abs(vg[same] - vr[same]) / yn[same]).max() < 1e-4
+    # the update (FP32 residual products) from the oracle's coding
+    v32 = vr.astype(np.float32)
+    Dr, vnr, unused = oracle.jau_update(w.Y, w.D0, ir, v32, n)
+    prm32 = dl.Params(p, n, m, s)
+    ws32 = dl.workspace(prm32)
+    Dg = dev(w.D0)
+    vng = dev(v32)
+    dl.jau_update(prm32, dev(w.Y), Dg, dev(ir, torch.int32), vng, ws32)
+    st = dl.read_stats(prm32, ws32)
+    assert st["unused_atoms"] == unused
+    assert np.abs(host(Dg).astype(np.float64) - Dr).max() < 1e-4
+    ynf = np.linalg.norm(w.Y.astype(np.float64), axis=1, keepdims=True)
+    assert (np.abs(host(vng).astype(np.float64) - vnr) / ynf).max() < 1e-4
