@@ -244,13 +244,22 @@ __device__ inline void rmse_refresh_body(const RmseArgs &a, int blk, int nblk)
 }
 
 // Sum of the nblk block partials in block order, and the error.
+// The first 256 threads of the workgroup take part (a larger workgroup's
+// other waves only pass the barriers), so the sum has the same bits in every
+// launch that runs it.
 __device__ inline void rmse_final_body(const RmseArgs &a, int nblk)
 {
     __shared__ double red4[4];
     double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-        v += a.partial[b];
-    const double tot = block_sum_f64(v, red4);
+    if (threadIdx.x < 256)
+        for (int b = threadIdx.x; b < nblk; b += 256)
+            v += a.partial[b];
+    v = wave_sum_f64(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0 && threadIdx.x < 256)
+        red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double tot = ((red4[0] + red4[1]) + red4[2]) + red4[3];
     if (threadIdx.x == 0) {
         a.out[0] = sqrt(tot / ((double)a.p * (double)a.m));
         if (!isfinite(tot))

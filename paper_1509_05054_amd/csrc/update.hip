@@ -144,19 +144,23 @@ __device__ inline void gsum_item(int it, int nr, int nsb, int &b, int &r)
 
 constexpr int kGsumRows = 8;  // residual rows in flight per lane
 
+// W waves per workgroup (64 W threads): 64 W / LPU atoms per range, at most
+// 64 (the caller keeps W <= LPU).  The sums do not depend on W or on the
+// ranges, only on the signal blocks.
+template <int W>
 __device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, int nblk)
 {
     __shared__ unsigned short pool[kGsumPool];  // the atoms' lists (entries of the block)
     __shared__ unsigned short ce[kGsumPool];    // each wave's entries of the range's atoms
     __shared__ unsigned char ck[kGsumPool];     // and their atoms within the range
-    __shared__ int wcnt[4][64];
-    __shared__ unsigned long long wmask[4][64];
+    __shared__ int wcnt[W][64];
+    __shared__ unsigned long long wmask[W][64];
     __shared__ int seg0[64], segn[64];
-    __shared__ int wbase[4];
+    __shared__ int wbase[W];
     const int p = a.p, s = a.s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpu = lanes_per_user(p);
-    const int R = 256 / lpu;  // atoms per range (at most 64: p >= 16)
+    const int R = 64 * W / lpu;  // atoms per range
     const int nr = (a1 - a0 + R - 1) / R;
     const int B = a.sig_block, nsb = a.nsb;
     const int grp = threadIdx.x / lpu;  // atom of this lane group within the range
@@ -175,11 +179,11 @@ __device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, i
         const int i0 = b * B;
         const int len = (min(a.m, i0 + B) - i0) * s;
         const size_t e0 = (size_t)i0 * s;
-        const int per = ((len + 255) / 256) * 64;  // entries per wave
+        const int per = ((len + 64 * W - 1) / (64 * W)) * 64;  // entries per wave
         const int w0 = min(len, wave * per), w1 = min(len, w0 + per);
         // this lane's entries w0 + lane + 64 c, as atoms of the range (-1:
         // another atom or an unused slot), all loaded before any is used
-        constexpr int kPer = kGsumPool / 256;
+        constexpr int kPer = kGsumPool / (64 * W);
         int kk[kPer];
 #pragma unroll
         for (int c = 0; c < kPer; ++c) {
@@ -193,7 +197,7 @@ __device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, i
             kk[c] = k;
         }
         __syncthreads();  // the previous item's lists are no longer read
-        for (int t = threadIdx.x; t < 4 * 64; t += blockDim.x) {
+        for (int t = threadIdx.x; t < W * 64; t += blockDim.x) {
             (&wcnt[0][0])[t] = 0;
             (&wmask[0][0])[t] = 0ull;
         }
@@ -204,11 +208,13 @@ __device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, i
                 atomicAdd(&wcnt[wave][kk[c]], 1);
         __syncthreads();
         if (wave == 0) {
-            const int v0 = lane < rr ? wcnt[0][lane] : 0;
-            const int v1 = lane < rr ? wcnt[1][lane] : 0;
-            const int v2 = lane < rr ? wcnt[2][lane] : 0;
-            const int v3 = lane < rr ? wcnt[3][lane] : 0;
-            const int tot = v0 + v1 + v2 + v3;
+            int v[W];
+            int tot = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                v[w] = lane < rr ? wcnt[w][lane] : 0;
+                tot += v[w];
+            }
             int x = tot;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -219,20 +225,22 @@ __device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, i
             const int ex = x - tot;
             seg0[lane] = ex;
             segn[lane] = tot;
-            wcnt[0][lane] = ex;
-            wcnt[1][lane] = ex + v0;
-            wcnt[2][lane] = ex + v0 + v1;
-            wcnt[3][lane] = ex + v0 + v1 + v2;
-            // each wave's compacted run starts after the earlier waves' runs
-            int t0 = v0, t1 = v1, t2 = v2;
+            // per (wave, atom) offsets, and each wave's compacted run after
+            // the earlier waves' runs
+            int run = ex, before = 0, wb = 0;
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                t0 += __shfl_xor(t0, off);
-                t1 += __shfl_xor(t1, off);
-                t2 += __shfl_xor(t2, off);
+            for (int w = 0; w < W; ++w) {
+                wcnt[w][lane] = run;
+                run += v[w];
+                int tw = v[w];
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1)
+                    tw += __shfl_xor(tw, off);
+                wb = lane == w ? before : wb;
+                before += tw;
             }
-            if (lane < 4)
-                wbase[lane] = (lane > 0 ? t0 : 0) + (lane > 1 ? t1 : 0) + (lane > 2 ? t2 : 0);
+            if (lane < W)
+                wbase[lane] = wb;
         }
         __syncthreads();
         // compaction of the wave's entries of the range's atoms, in order
@@ -307,14 +315,15 @@ __device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, i
 }
 
 // The optional last workgroup sums a carried error's partials.
-__global__ __launch_bounds__(256) void gsum_kernel(UpdateArgs a, int a0, int a1, RmseArgs err,
-                                                   int eb)
+template <int W>
+__global__ __launch_bounds__(64 * W) void gsum_kernel(UpdateArgs a, int a0, int a1, RmseArgs err,
+                                                      int eb)
 {
     if (eb > 0 && blockIdx.x == gridDim.x - 1) {
         rmse_final_body(err, eb);
         return;
     }
-    gsum_body(a, a0, a1, blockIdx.x, gridDim.x - (eb > 0 ? 1 : 0));
+    gsum_body<W>(a, a0, a1, blockIdx.x, gridDim.x - (eb > 0 ? 1 : 0));
 }
 
 // ---- pass 2: d_j' and the AK-SVD representation refresh ------------------
@@ -711,7 +720,7 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateArgs *__restri
         const int t = cur.it - own.b0, nt = own.b1 - own.b0;
         if (STAGE == 0) {
             if (a.sig_block)
-                gsum_body(a, 0, a.n, t, nt);
+                gsum_body<4>(a, 0, a.n, t, nt);
             else
                 pass1_body(a, 0, a.n, t, nt);
         } else
@@ -851,6 +860,24 @@ int gsum_items(const dl_params &prm)
     return gsum_signal_blocks(prm) * ((prm.n + R - 1) / R);
 }
 
+// Waves per workgroup of a single problem's pass 1 by signal blocks: the most
+// (up to 16, and at most LPU, so that a range holds at most 64 atoms) whose
+// items still number at least kGsumMinItems (measured at p = 64, n = 256:
+// m = 16384 takes 8, 336 -> 345 M signals*iters/s against 4, where 16 gave
+// 340 M; m = 262144 takes 16, 547 -> 578 M).
+constexpr int kGsumMinItems = 512;
+static int gsum_waves(int p, int n, int nsb)
+{
+    const int lpu = host_lanes_per_user(p);
+    int w = 4;
+    for (int c = 8; c <= 16 && c <= lpu; c *= 2) {
+        const int R = 64 * c / lpu;
+        if ((long long)nsb * ((n + R - 1) / R) >= kGsumMinItems)
+            w = c;
+    }
+    return w;
+}
+
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st, const RmseArgs *err)
 {
     const int gs = a.group_size >= a.n ? a.n : a.group_size;
@@ -868,12 +895,19 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st, const RmseArgs *er
         if (a.sig_block) {
             // one group (a0 = 0, a1 = n); at most 4096 workgroups, a multiple
             // of 8 when the items are more, so an item keeps its XCD
-            const int R = 256 / host_lanes_per_user(a.p);
+            const int W = gsum_waves(a.p, a1 - a0, a.nsb);
+            const int R = 64 * W / host_lanes_per_user(a.p);
             const int items = a.nsb * ((a1 - a0 + R - 1) / R);
             const int g1 = items < 4096 ? items : 4096;
             const int eb = err ? rmse_blocks_dev(err->m) : 0;
-            hipLaunchKernelGGL(gsum_kernel, dim3(g1 + (err ? 1 : 0)), dim3(256), 0, st, a, a0, a1,
-                               err ? *err : RmseArgs{}, eb);
+            const dim3 grid(g1 + (err ? 1 : 0));
+            const RmseArgs e = err ? *err : RmseArgs{};
+            if (W == 16)
+                hipLaunchKernelGGL(gsum_kernel<16>, grid, dim3(1024), 0, st, a, a0, a1, e, eb);
+            else if (W == 8)
+                hipLaunchKernelGGL(gsum_kernel<8>, grid, dim3(512), 0, st, a, a0, a1, e, eb);
+            else
+                hipLaunchKernelGGL(gsum_kernel<4>, grid, dim3(256), 0, st, a, a0, a1, e, eb);
         } else {
             hipLaunchKernelGGL(pass1_kernel, dim3(grid), dim3(256), 0, st, a, a0, a1);
         }
