@@ -262,18 +262,16 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         constexpr int k = decltype(kc)::value;
         if (k >= s || !__any(active))
             return false;
-        // 1. argmax over the group (selected atoms are NaN), lowest index on
-        // ties.  Per lane, each |alpha| has its last four mantissa bits
-        // replaced by 15 - c, so one float maximum (which never returns a NaN
-        // over a number) also picks the lowest c among values equal in their
-        // other bits; magnitudes are compared to 2^-19 relative.
-        float key = 0.f;
+        // 1. argmax over the group (selected atoms are NaN), lowest index on ties
+        float best = -1.f;
+        int bidx = 0x7fffffff;
 #pragma unroll
-        for (int c = 0; c < NPL; ++c)
-            key = fmaxf(key, __int_as_float((f_bits(alpha[c]) & 0x7ffffff0) | (15 - c)));
-        const int kb = f_bits(key);
-        float best = __int_as_float(kb & ~15);
-        int bidx = a_first + 15 - (kb & 15);
+        for (int c = 0; c < NPL; ++c) {
+            const float v = fabsf(alpha[c]);
+            const bool b = v > best;
+            best = b ? v : best;
+            bidx = b ? a_first + c : bidx;
+        }
         group_argmax<LPS>(best, bidx);
         if constexpr (WPS == 2) {
             if (l == 0) {
