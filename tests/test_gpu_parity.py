@@ -34,7 +34,8 @@ def _patch_problem(p, n, m, seed):
 
 # ---------------------------------------------------------------- GEMMs
 @pytest.mark.parametrize("p,n,m", [(16, 32, 1024), (64, 256, 1000), (36, 72, 333),
-                                   (144, 576, 130), (256, 1024, 2050), (4, 1, 1)])
+                                   (144, 576, 130), (256, 1024, 2050), (4, 1, 1),
+                                   (64, 200, 16391), (64, 256, 16384), (32, 256, 9)])
 def test_gram_and_correlations(p, n, m):
     note(f"gemm p={p} n={n} m={m}")
     rng = np.random.default_rng(p + n + m)
@@ -53,6 +54,12 @@ def test_gram_and_correlations(p, n, m):
     errG = np.abs(host(G) - D64 @ D64.T) / np.outer(nd, nd)
     errA = np.abs(host(A0) - Y64 @ D64.T) / np.outer(ny, nd)
     assert errG.max() < 2e-6 and errA.max() < 2e-6, (errG.max(), errA.max())
+    # both products in one launch: the same bits as the separate launches
+    G2 = torch.full((n, n), float("nan"), device="cuda")
+    A02 = torch.full((m, n), float("nan"), device="cuda")
+    dl.products(prm, Dg, dev(Y), G2, A02, dl.workspace(prm))
+    torch.cuda.synchronize()
+    assert torch.equal(G2, G) and torch.equal(A02, A0)
 
 
 # ---------------------------------------------------------------- OMP
