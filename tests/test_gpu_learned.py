@@ -221,7 +221,8 @@ def test_learned_pipeline_gains_over_untrained_network():
     """Plain iterations record (signal, support) pairs; the network trained on
     them proposes candidates that cover OMP's supports far better than the
     untrained network, so far fewer signals fall back to OMP, and the learned
-    iterations keep the error close to the plain method's."""
+    iterations end at the plain method's error: within 1% of the plain
+    iterations' final RMSE (the equal-error bar of the learned reading)."""
     note("learned pipeline")
     w = synth.workload("patches_p64_n256_s6_m262144", m=16384)
     p, n, s, m = w.p, w.n, w.s, w.m
@@ -284,7 +285,7 @@ def test_learned_pipeline_gains_over_untrained_network():
           f"rmse learned={rl[-1]:.6f} plain={rp[-1]:.6f}")
     assert r_trained > r_untrained + 0.3
     assert fb_trained < fb_untrained
-    assert abs(rl[-1] - rp[-1]) / rp[-1] < 0.05
+    assert abs(rl[-1] - rp[-1]) / rp[-1] <= 0.01
 
 
 def test_audit_on_every_iteration_is_the_plain_iteration():
