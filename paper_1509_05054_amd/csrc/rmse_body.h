@@ -136,6 +136,60 @@ __device__ inline void rmse_body(const RmseArgs &a, int blk, int nblk)
         a.partial[blk] = tot_blk;
 }
 
+// The refreshed coefficients and residual rows of the RU signals [ilc[u]] of
+// a lane group in a staged signal block (slots in sIdx/sVal/sCos, rows of y
+// and of the coding residual e in ey/eo), their squares added to acc.
+template <int RU>
+__device__ inline void refresh_rows(const RmseArgs &a, int i0, const bool (&on)[RU],
+                                    const int (&ilc)[RU], f32x4 (&ey)[RU], const f32x4 (&eo)[RU],
+                                    const int *sIdx, const float *sVal, const float *sCos,
+                                    int lpu, int q, int lane, double &acc)
+{
+    const int p = a.p, s = a.s;
+    // TS slots at a time: all their atom rows are loaded before any is used,
+    // so the loads are in flight together (the stores of x' between them
+    // would otherwise order each slot's loads after the previous slot's
+    // store)
+    constexpr int TS = 4;
+    for (int t0 = 0; t0 < s; t0 += TS) {
+        f32x4 dn[RU][TS];
+        float x[RU][TS], cj[RU][TS];
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int v = 0; v < TS; ++v) {
+                const int t = t0 + v < s ? t0 + v : t0;
+                const int r = ilc[u] * s + t;
+                const int j = sIdx[r];
+                x[u][v] = on[u] ? sVal[r] : 0.f;
+                cj[u][v] = on[u] ? sCos[r] : __builtin_nanf("");
+                dn[u][v] = load4(a.D + (size_t)j * p, q, p);
+            }
+#pragma unroll
+        for (int v = 0; v < TS; ++v) {
+            if (t0 + v >= s)
+                break;  // uniform over the workgroup
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                float part = eo[u][0] * dn[u][v][0] + eo[u][1] * dn[u][v][1] +
+                             eo[u][2] * dn[u][v][2] + eo[u][3] * dn[u][v][3];
+                for (int off = 1; off < lpu; off <<= 1)
+                    part += __shfl_xor(part, off);
+                const bool keep = cj[u][v] != cj[u][v];  // NaN: kept
+                const float xn = keep ? x[u][v] : part + x[u][v] * cj[u][v];
+                if (on[u] && (lane % lpu) == 0)
+                    a.valn[(size_t)(i0 + ilc[u]) * s + t0 + v] = xn;
+                ey[u] -= dn[u][v] * xn;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc += (double)ey[u][r] * (double)ey[u][r];
+}
+
 // The same partials with the coefficient refresh of the atom update (all
 // atoms in one group): per slot, x' = (e + d x)^T d' formed as
 // e^T d' + x (d^T d') with pass 2's operations and order (so the same bits;
@@ -194,49 +248,109 @@ __device__ inline void rmse_refresh_body(const RmseArgs &a, int blk, int nblk)
                 ey[u] = on[u] ? load4(a.Y + (size_t)(i0 + il) * p, q, p) : zero;
                 eo[u] = on[u] ? load4(a.E + (size_t)(i0 + il) * p, q, p) : zero;
             }
-            // TS slots at a time: all their atom rows are loaded before any
-            // is used, so the loads are in flight together (the stores of x'
-            // between them would otherwise order each slot's loads after the
-            // previous slot's store)
-            constexpr int TS = 4;
-            for (int t0 = 0; t0 < s; t0 += TS) {
-                f32x4 dn[RU][TS];
-                float x[RU][TS], cj[RU][TS];
-#pragma unroll
-                for (int u = 0; u < RU; ++u)
-#pragma unroll
-                    for (int v = 0; v < TS; ++v) {
-                        const int t = t0 + v < s ? t0 + v : t0;
-                        const int r = ilc[u] * s + t;
-                        const int j = sIdx[r];
-                        x[u][v] = on[u] ? sVal[r] : 0.f;
-                        cj[u][v] = on[u] ? sCos[r] : __builtin_nanf("");
-                        dn[u][v] = load4(a.D + (size_t)j * p, q, p);
-                    }
-#pragma unroll
-                for (int v = 0; v < TS; ++v) {
-                    if (t0 + v >= s)
-                        break;  // uniform over the workgroup
-#pragma unroll
-                    for (int u = 0; u < RU; ++u) {
-                        float part = eo[u][0] * dn[u][v][0] + eo[u][1] * dn[u][v][1] +
-                                     eo[u][2] * dn[u][v][2] + eo[u][3] * dn[u][v][3];
-                        for (int off = 1; off < lpu; off <<= 1)
-                            part += __shfl_xor(part, off);
-                        const bool keep = cj[u][v] != cj[u][v];  // NaN: kept
-                        const float xn = keep ? x[u][v] : part + x[u][v] * cj[u][v];
-                        if (on[u] && (lane % lpu) == 0)
-                            a.valn[(size_t)(i0 + ilc[u]) * s + t0 + v] = xn;
-                        ey[u] -= dn[u][v] * xn;
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < RU; ++u)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    acc += (double)ey[u][r] * (double)ey[u][r];
+            refresh_rows<RU>(a, i0, on, ilc, ey, eo, sIdx, sVal, sCos, lpu, q, lane, acc);
         }
+    }
+    const double tot_blk = block_sum_f64(acc, red4);
+    if (threadIdx.x == 0)
+        a.partial[blk] = tot_blk;
+}
+
+// The refreshing partials of the error launch of its own, software
+// pipelined over the signal blocks of a workgroup: the next block's slots
+// and its rows of y and e are loaded while the current block is computed, and
+// d^T d' of every atom comes from a table staged in LDS once, so a block
+// waits on its atom rows only.  The arithmetic, the assignment of signals to
+// lanes and the order of every sum are those of rmse_refresh_body (the same
+// bits).  Requires p <= 64 (one pass of the lane groups covers a block) and
+// n <= kRmseCosTab.
+constexpr int kRmseCosTab = 2048;
+__device__ inline void rmse_refresh_body_pf(const RmseArgs &a, int blk, int nblk)
+{
+    __shared__ double red4[4];
+    __shared__ int sIdx[kRmseSignals * 16];
+    __shared__ float sVal[kRmseSignals * 16];
+    __shared__ float sCos[kRmseSignals * 16];
+    __shared__ float sTab[kRmseCosTab];
+    constexpr int RU = 2;
+    constexpr int CPT = kRmseSignals * 16 / 256;  // staged slots per thread
+    const int s = a.s, n = a.n, p = a.p;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lpu = lanes_per_user(p);
+    const int upw = 64 / lpu;
+    const int sub = lane / lpu;
+    const int q = 4 * (lane % lpu);
+    const int G = 4 * upw;
+    const int il0 = wave * upw + sub;  // G * RU >= kRmseSignals: one pass per block
+    const f32x4 zero = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        sTab[j] = (a.rule == DL_RULE_AKSVD && a.atom_state[j] == 0) ? a.atom_cos[j]
+                                                                     : __builtin_nanf("");
+    double acc = 0.0;
+    const int nsb = (a.m + kRmseSignals - 1) / kRmseSignals;
+    int pj[CPT];
+    float px[CPT];
+    f32x4 py[RU], pe[RU];
+    auto prefetch = [&](int sb) {
+        const int i0 = sb * kRmseSignals;
+        const int nsig = min(kRmseSignals, a.m - i0);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int r = (int)threadIdx.x + 256 * c;
+            pj[c] = -1;
+            px[c] = 0.f;
+            if (r < nsig * s) {
+                pj[c] = a.idx[(size_t)i0 * s + r];
+                px[c] = a.val_old[(size_t)i0 * s + r];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int il = il0 + u * G;
+            py[u] = il < nsig ? load4(a.Y + (size_t)(i0 + il) * p, q, p) : zero;
+            pe[u] = il < nsig ? load4(a.E + (size_t)(i0 + il) * p, q, p) : zero;
+        }
+    };
+    if (blk < nsb)
+        prefetch(blk);
+    for (int sb = blk; sb < nsb; sb += nblk) {
+        const int i0 = sb * kRmseSignals;
+        const int nsig = min(kRmseSignals, a.m - i0);
+        __syncthreads();  // the previous block's slots are no longer read (and sTab is staged)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int r = (int)threadIdx.x + 256 * c;
+            if (r < nsig * s) {
+                int j = pj[c];
+                float x = px[c];
+                float cj = __builtin_nanf("");
+                if (j < 0 || j >= n) {
+                    j = 0;  // unused slot: row 0, coefficient 0 (kept)
+                    x = 0.f;
+                } else {
+                    cj = sTab[j];
+                }
+                sIdx[r] = j;
+                sVal[r] = x;
+                sCos[r] = cj;
+            }
+        }
+        __syncthreads();
+        f32x4 ey[RU], eo[RU];
+        bool on[RU];
+        int ilc[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int il = il0 + u * G;
+            on[u] = il < nsig;
+            ilc[u] = on[u] ? il : il0;
+            ey[u] = py[u];
+            eo[u] = pe[u];
+        }
+        if (sb + nblk < nsb)
+            prefetch(sb + nblk);
+        if (il0 < nsig)
+            refresh_rows<RU>(a, i0, on, ilc, ey, eo, sIdx, sVal, sCos, lpu, q, lane, acc);
     }
     const double tot_blk = block_sum_f64(acc, red4);
     if (threadIdx.x == 0)

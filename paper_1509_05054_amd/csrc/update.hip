@@ -628,6 +628,11 @@ __global__ __launch_bounds__(256) void rmse_kernel(RmseArgs a)
         rmse_body(a, blockIdx.x, gridDim.x);
 }
 
+__global__ __launch_bounds__(256) void rmse_pf_kernel(RmseArgs a)
+{
+    rmse_refresh_body_pf(a, blockIdx.x, gridDim.x);
+}
+
 __global__ __launch_bounds__(256) void rmse_final_kernel(RmseArgs a, int nblk)
 {
     rmse_final_body(a, nblk);
@@ -993,7 +998,9 @@ hipError_t launch_rmse(const RmseArgs &a, hipStream_t st)
 {
     const int nb = rmse_blocks(a.m);
     prof_begin(DL_K_RMSE, st);
-    if (a.refresh)
+    if (a.refresh && a.p <= 64 && a.n <= kRmseCosTab)
+        hipLaunchKernelGGL(rmse_pf_kernel, dim3(nb), dim3(256), 0, st, a);
+    else if (a.refresh)
         hipLaunchKernelGGL(rmse_kernel<true>, dim3(nb), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(rmse_kernel<false>, dim3(nb), dim3(256), 0, st, a);
