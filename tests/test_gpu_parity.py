@@ -435,14 +435,18 @@ C2 = "patches_p64_n256_s6_m16384"
 
 @pytest.mark.parametrize("wl,m,rule", [(C2, 3000, dl.RULE_AKSVD), (C2, 20000, dl.RULE_AKSVD),
                                        (C2, 3000, dl.RULE_SGK), (C2, 20000, dl.RULE_SGK),
-                                       ("patches_p256_n1024_s12_m65536", 3000, dl.RULE_AKSVD)])
+                                       ("patches_p256_n1024_s12_m65536", 3000, dl.RULE_AKSVD),
+                                       (C2, 40001, dl.RULE_AKSVD),
+                                       ("recovery_p16_n32_s3_m1024", 40001, dl.RULE_AKSVD)])
 def test_iterate_refresh_in_error_pass_bitwise(wl, m, rule):
     """With all atoms in one group the iteration forms the refreshed X in the
     error pass; up to 16384 signals the error of iteration k is carried by
     iteration k+1's coding launch (partials, with the refresh; X and E then
     alternate between two buffers) or, for the two-wave coding shape (n =
     1024, s = 12), by its products launch, and by its CSR scan launch (final
-    sum); above that it runs in launches of its own (the SGK rule keeps X).
+    sum); above that it runs in launches of its own (the SGK rule keeps X),
+    which at p <= 64 pipeline the signal blocks of a workgroup (m = 40001:
+    1251 blocks over 1024 workgroups, the last block one signal).
     Three iterations equal the explicit coding, update (refresh in pass 2)
     and error calls of every iteration bit for bit: the same errors of
     iterations 0 and 1 (carried at m = 3000) and 2 (always on its own), the
