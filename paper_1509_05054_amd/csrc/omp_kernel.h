@@ -144,6 +144,28 @@ __device__ inline float group_bcast(float v)
     }
 }
 
+// group_bcast from lane t, where t is the index of an unrolled loop (the
+// switch folds to its one case).
+template <int LPS>
+__device__ __forceinline__ float group_bcast_at(float v, int t)
+{
+    switch (t) {
+#define DL_BCAST_AT(T)                       \
+    case T:                                  \
+        if constexpr (T < LPS)               \
+            return group_bcast<LPS, T>(v);   \
+        break;
+        DL_BCAST_AT(0) DL_BCAST_AT(1) DL_BCAST_AT(2) DL_BCAST_AT(3)
+        DL_BCAST_AT(4) DL_BCAST_AT(5) DL_BCAST_AT(6) DL_BCAST_AT(7)
+        DL_BCAST_AT(8) DL_BCAST_AT(9) DL_BCAST_AT(10) DL_BCAST_AT(11)
+        DL_BCAST_AT(12) DL_BCAST_AT(13) DL_BCAST_AT(14) DL_BCAST_AT(15)
+#undef DL_BCAST_AT
+    default:
+        break;
+    }
+    return v;
+}
+
 template <int NPL>
 using vec_t = float __attribute__((ext_vector_type(NPL)));
 
@@ -237,20 +259,18 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         if (a_first + c >= n)
             alpha[c] = __builtin_nanf("");
 
+    // Row t of L and the values of step t live in lane t of the group (c_t,
+    // 1 / L[t][t] and the selected atom), and are broadcast where the other
+    // lanes need them: registers held per lane for every step would cost the
+    // coding kernel occupancy at large s.
     vec_t<NPL> u[US];
     float Lrow[SMAX];     // row l of L (this lane's row)
-    float cv[SMAX];       // c_t, the same in every lane of the group
-    float dgi[SMAX];      // 1 / L[t][t]
+    float cown = 0.f;     // c_l
     float rdg = 1.f;      // 1 / L[l][l], this lane's own diagonal
-    int js[SMAX];         // selected atoms
     int selj = -1;        // this lane's atom (row l)
 #pragma unroll
-    for (int t = 0; t < SMAX; ++t) {
+    for (int t = 0; t < SMAX; ++t)
         Lrow[t] = 0.f;
-        cv[t] = 0.f;
-        dgi[t] = 1.f;
-        js[t] = 0;
-    }
     bool active = valid && isfinite(ynorm);
     if (lead && valid && !isfinite(ynorm) && l == 0)
         atomicAdd(&a.ctl->nonfinite, 1ull);
@@ -374,7 +394,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
 #pragma unroll
         for (int t = 0; t < US; ++t)
             if (t < k)
-                ck -= w[t] * cv[t];
+                ck -= w[t] * group_bcast_at<LPS>(cown, t);
         ck *= inv;
 
         // 4. u_k and the correlation update (not needed after the last step)
@@ -390,13 +410,6 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
             }
         }
         if (ok) {
-#pragma unroll
-            for (int t = 0; t < SMAX; ++t)
-                if (t == k) {
-                    cv[t] = ck;
-                    dgi[t] = inv;
-                    js[t] = j;
-                }
             if (l == k) {
 #pragma unroll
                 for (int t = 0; t < US; ++t)
@@ -407,6 +420,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
                     if (t == k)
                         Lrow[t] = delta;
                 rdg = inv;
+                cown = ck;
                 selj = j;
             }
             kg = k + 1;
@@ -423,7 +437,8 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
     for (int r = SMAX - 1; r >= 0; --r) {
         const float part = (l > r && l < kg) ? Lrow[r] * xown : 0.f;
         const float ssum = group_sum<LPS>(part);
-        const float xr = (cv[r] - ssum) * dgi[r];
+        const float xr =
+            (group_bcast_at<LPS>(cown, r) - ssum) * group_bcast_at<LPS>(rdg, r);
         xs[r] = r < kg ? xr : 0.f;
         if (l == r)
             xown = xs[r];
@@ -441,6 +456,12 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
     // kg hold atom 0 with a zero coefficient, so the row loads need no
     // per-lane branch and are in flight together
     if (a.E || a.rnorm) {
+        int js[SMAX];  // selected atoms; atom 0 past kg
+#pragma unroll
+        for (int t = 0; t < SMAX; ++t) {
+            const int jt = f_bits(group_bcast_at<LPS>(bits_f(selj), t));
+            js[t] = jt < 0 ? 0 : jt;
+        }
         float esq = 0.f;
         if (valid)
             for (int q = 4 * l; q < p; q += 4 * LPS) {
