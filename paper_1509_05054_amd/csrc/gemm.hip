@@ -20,7 +20,6 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kTM = 2;                // 16x16 MFMA tiles per wave along M
 constexpr int kTN = 4;                // 16x16 MFMA tiles per wave along N
 constexpr int kBlockN = 2 * 16 * kTN;
 

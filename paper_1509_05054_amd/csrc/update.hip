@@ -443,7 +443,7 @@ __device__ inline void pass2_body(const UpdateArgs &a, int a0, int a1, int blk, 
     __shared__ float sX[kChunk];
     __shared__ float sDn[256];
     __shared__ float red4[4];
-    const int p = a.p, s = a.s;
+    const int p = a.p;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpu = lanes_per_user(p);
     const int upw = 64 / lpu;
