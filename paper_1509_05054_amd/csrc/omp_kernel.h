@@ -282,16 +282,18 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         constexpr int k = decltype(kc)::value;
         if (k >= s || !__any(active))
             return false;
-        // 1. argmax over the group (selected atoms are NaN), lowest index on ties
+        // 1. argmax over the group (selected atoms are NaN), lowest index on ties:
+        // the lane's largest |alpha| by a max chain (which passes over NaN),
+        // then the first of its atoms holding it
         float best = -1.f;
-        int bidx = 0x7fffffff;
 #pragma unroll
-        for (int c = 0; c < NPL; ++c) {
-            const float v = fabsf(alpha[c]);
-            const bool b = v > best;
-            best = b ? v : best;
-            bidx = b ? a_first + c : bidx;
-        }
+        for (int c = 0; c < NPL; ++c)
+            best = fmaxf(best, fabsf(alpha[c]));
+        int cfirst = NPL;
+#pragma unroll
+        for (int c = NPL - 1; c >= 0; --c)
+            cfirst = fabsf(alpha[c]) == best ? c : cfirst;
+        int bidx = cfirst < NPL ? a_first + cfirst : 0x7fffffff;
         group_argmax<LPS>(best, bidx);
         if constexpr (WPS == 2) {
             if (l == 0) {
