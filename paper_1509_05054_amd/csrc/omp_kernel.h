@@ -72,6 +72,21 @@ __device__ inline void take_better(float &v, int &ix, float ov, int oi)
     ix = b ? oi : ix;
 }
 
+// The value of a 64-lane group from its four row values (every lane of row r
+// holding v_r): DPP row broadcasts combine rows 0+1 into row 1 and 2+3 into
+// row 3, then row 1 into row 3, and lane 63 is read out, so the result is
+// op(op(v_0, v_1), op(v_2, v_3)) (for a sum, the association of the xor
+// butterfly across rows, whose result every lane held) and wave-uniform.
+// The cross-row steps of the butterfly go through the LDS crossbar
+// (ds_bpermute); these stay in the VALU.
+template <class Op>
+__device__ inline int rows64_combine(int x, int identity, Op op)
+{
+    x = op(x, __builtin_amdgcn_update_dpp(identity, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    x = op(x, __builtin_amdgcn_update_dpp(identity, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
 // All-reduce over groups of LPS lanes: the maximum of v, then the lowest
 // index among the lanes that hold it.  v is -1 or a non-negative float (never
 // NaN), whose order is that of its bits as signed integers, so both are
@@ -89,10 +104,10 @@ __device__ inline int group_min_max(int x, bool take_max)
         x = pick(x, dpp_fold<0x141>(x));
     if constexpr (LPS >= 16)
         x = pick(x, dpp_fold<0x140>(x));
+    if constexpr (LPS == 64)
+        return rows64_combine(x, take_max ? (int)0x80000000 : 0x7fffffff, pick);
     if constexpr (LPS >= 32)
         x = pick(x, __shfl_xor(x, 16));
-    if constexpr (LPS >= 64)
-        x = pick(x, __shfl_xor(x, 32));
     return x;
 }
 
@@ -115,10 +130,12 @@ __device__ inline float group_sum(float v)
         v += bits_f(dpp<0x141>(f_bits(v)));
     if constexpr (LPS >= 16)
         v += bits_f(dpp<0x140>(f_bits(v)));
+    if constexpr (LPS == 64)
+        return bits_f(rows64_combine(f_bits(v), 0, [](int a, int b) {
+            return f_bits(bits_f(a) + bits_f(b));
+        }));
     if constexpr (LPS >= 32)
         v += __shfl_xor(v, 16);
-    if constexpr (LPS >= 64)
-        v += __shfl_xor(v, 32);
     return v;
 }
 
