@@ -42,6 +42,33 @@ __host__ __device__ inline int rmse_blocks_dev(int m)
     return b < kRmseMaxBlocks ? b : kRmseMaxBlocks;
 }
 
+// Sum over groups of lpu consecutive lanes (lpu a power of two, every lane
+// gets its group's sum), in the association of the xor butterfly: inside a
+// row of 16 lanes by DPP (xor 1 and xor 2 by quad permutes; the half-row and
+// row mirrors then pair the same quads and the same half-rows as xor 4 and
+// xor 8, and addition commutes, so every lane gets the same bits), across
+// rows by shuffles.  All lanes of a group must be active.
+template <int CTRL>
+__device__ inline float dpp_mov_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+__device__ inline float lanes_sum(float v, int lpu)
+{
+    if (lpu >= 2)
+        v += dpp_mov_f<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    if (lpu >= 4)
+        v += dpp_mov_f<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    if (lpu >= 8)
+        v += dpp_mov_f<0x141>(v);  // row_half_mirror
+    if (lpu >= 16)
+        v += dpp_mov_f<0x140>(v);  // row_mirror
+    for (int off = 16; off < lpu; off <<= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
 __device__ inline double wave_sum_f64(double v)
 {
 #pragma unroll
@@ -173,8 +200,7 @@ __device__ inline void refresh_rows(const RmseArgs &a, int i0, const bool (&on)[
             for (int u = 0; u < RU; ++u) {
                 float part = eo[u][0] * dn[u][v][0] + eo[u][1] * dn[u][v][1] +
                              eo[u][2] * dn[u][v][2] + eo[u][3] * dn[u][v][3];
-                for (int off = 1; off < lpu; off <<= 1)
-                    part += __shfl_xor(part, off);
+                part = lanes_sum(part, lpu);
                 const bool keep = cj[u][v] != cj[u][v];  // NaN: kept
                 const float xn = keep ? x[u][v] : part + x[u][v] * cj[u][v];
                 if (on[u] && (lane % lpu) == 0)

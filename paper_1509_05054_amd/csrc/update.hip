@@ -423,8 +423,7 @@ __device__ inline void pass2_refresh(const UpdateArgs &a, float cj, f32x4 dn, co
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             float part = e[u][0] * dn[0] + e[u][1] * dn[1] + e[u][2] * dn[2] + e[u][3] * dn[3];
-            for (int off = 1; off < lpu; off <<= 1)
-                part += __shfl_xor(part, off);
+            part = lanes_sum(part, lpu);
             if (pos[u] >= 0 && (lane % lpu) == 0)
                 a.valn[pos[u]] = part + x[u] * cj;
         }
