@@ -111,6 +111,41 @@ __global__ __launch_bounds__(256) void pass1_kernel(UpdateArgs a, int a0, int a1
     pass1_body(a, a0, a1, blockIdx.x, gridDim.x);
 }
 
+template <int CTRL, bool BC>
+__device__ inline int dpp_i(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, BC);
+}
+
+// Integer sum over the wave (every lane gets it): within rows by DPP, across
+// rows by reading one lane of each row.  Integer addition is exact, so the
+// order is free.
+__device__ inline int wave_sum_i32(int x)
+{
+    x += dpp_i<0xB1, false>(x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_i<0x4E, false>(x);   // quad_perm [2, 3, 0, 1]
+    x += dpp_i<0x141, false>(x);  // row_half_mirror
+    x += dpp_i<0x140, false>(x);  // row_mirror
+    return __builtin_amdgcn_readlane(x, 0) + __builtin_amdgcn_readlane(x, 16) +
+           __builtin_amdgcn_readlane(x, 32) + __builtin_amdgcn_readlane(x, 48);
+}
+
+// Inclusive prefix sum over the wave's lanes: a scan inside each row of 16 by
+// DPP row shifts (lanes shifted in from outside the row read 0), then the
+// totals of the earlier rows.
+__device__ inline int wave_scan_i32(int x)
+{
+    x += dpp_i<0x111, true>(x);  // row_shr:1
+    x += dpp_i<0x112, true>(x);  // row_shr:2
+    x += dpp_i<0x114, true>(x);  // row_shr:4
+    x += dpp_i<0x118, true>(x);  // row_shr:8
+    const int t0 = __builtin_amdgcn_readlane(x, 15);
+    const int t1 = __builtin_amdgcn_readlane(x, 31);
+    const int t2 = __builtin_amdgcn_readlane(x, 47);
+    const int row = (int)(threadIdx.x & 63) >> 4;
+    return x + (row >= 1 ? t0 : 0) + (row >= 2 ? t1 : 0) + (row >= 3 ? t2 : 0);
+}
+
 __device__ inline void wave_lds_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -215,13 +250,7 @@ __device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, i
                 v[w] = lane < rr ? wcnt[w][lane] : 0;
                 tot += v[w];
             }
-            int x = tot;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int y = __shfl_up(x, off);
-                if (lane >= off)
-                    x += y;
-            }
+            const int x = wave_scan_i32(tot);
             const int ex = x - tot;
             seg0[lane] = ex;
             segn[lane] = tot;
@@ -232,10 +261,7 @@ __device__ inline void gsum_body(const UpdateArgs &a, int a0, int a1, int blk, i
             for (int w = 0; w < W; ++w) {
                 wcnt[w][lane] = run;
                 run += v[w];
-                int tw = v[w];
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1)
-                    tw += __shfl_xor(tw, off);
+                const int tw = wave_sum_i32(v[w]);
                 wb = lane == w ? before : wb;
                 before += tw;
             }
