@@ -48,10 +48,11 @@ __host__ __device__ inline int rmse_blocks_dev(int m)
 // row mirrors then pair the same quads and the same half-rows as xor 4 and
 // xor 8, and addition commutes, so every lane gets the same bits), across
 // rows by shuffles.  All lanes of a group must be active.
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ inline float dpp_mov_f(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, false));
 }
 
 __device__ inline float lanes_sum(float v, int lpu)
@@ -67,6 +68,18 @@ __device__ inline float lanes_sum(float v, int lpu)
     for (int off = 16; off < lpu; off <<= 1)
         v += __shfl_xor(v, off);
     return v;
+}
+
+// Sum over the wave, the same in every lane: the row sums as in lanes_sum,
+// then rows 0 + 1 into row 1 and 2 + 3 into row 3 by DPP row broadcasts, row
+// 1 into row 3, and lane 63 read out, (r0 + r1) + (r2 + r3).  No LDS
+// crossbar operation.
+__device__ inline float wave_sum_f32(float v)
+{
+    v = lanes_sum(v, 16);
+    v += dpp_mov_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_mov_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ inline double wave_sum_f64(double v)

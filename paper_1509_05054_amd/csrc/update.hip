@@ -361,9 +361,7 @@ __global__ __launch_bounds__(64 * W) void gsum_kernel(UpdateArgs a, int a0, int 
 // users keep d_j; the items after the chunks handle them.
 __device__ inline float block_sum_f32(float v, float *red4)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off);
+    v = wave_sum_f32(v);
     __syncthreads();
     if ((threadIdx.x & 63) == 0)
         red4[threadIdx.x >> 6] = v;
