@@ -154,6 +154,34 @@ bool omp_config_ok(int n, int s, int lps, int npl);
 // Leading dimension used for G and A0 rows.
 inline int padded_n(int n) { return (n + 3) & ~3; }
 
+// The values of this lane and of lane ^ 16 (permlane16_swap: rows 2r and
+// 2r + 1 trade places) or lane ^ 32 (permlane32_swap: the wave's halves trade
+// places), as the pair (x, y) in an order that depends on the lane.  A sum
+// x + y or a max/min of the pair is the same in both lanes of a pair (both
+// commute), so one VALU instruction replaces a shuffle through the LDS
+// crossbar.
+__device__ inline void pair_xor16(int v, int &x, int &y)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    x = (int)r[0];
+    y = (int)r[1];
+}
+__device__ inline void pair_xor32(int v, int &x, int &y)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    x = (int)r[0];
+    y = (int)r[1];
+}
+__device__ inline float sum_xor(float v, int off)  // off: 16 or 32
+{
+    int x, y;
+    if (off == 16)
+        pair_xor16(__float_as_int(v), x, y);
+    else
+        pair_xor32(__float_as_int(v), x, y);
+    return __int_as_float(x) + __int_as_float(y);
+}
+
 struct CsrArgs {
     const int32_t *idx;  // [m][s]
     int32_t *blkcnt;     // [n][nb] per-(atom, block) counts, then offsets

@@ -106,8 +106,11 @@ __device__ inline int group_min_max(int x, bool take_max)
         x = pick(x, dpp_fold<0x140>(x));
     if constexpr (LPS == 64)
         return rows64_combine(x, take_max ? (int)0x80000000 : 0x7fffffff, pick);
-    if constexpr (LPS >= 32)
-        x = pick(x, __shfl_xor(x, 16));
+    if constexpr (LPS == 32) {
+        int u, w;
+        pair_xor16(x, u, w);  // this lane's value and lane ^ 16's
+        x = pick(u, w);
+    }
     return x;
 }
 
@@ -134,8 +137,8 @@ __device__ inline float group_sum(float v)
         return bits_f(rows64_combine(f_bits(v), 0, [](int a, int b) {
             return f_bits(bits_f(a) + bits_f(b));
         }));
-    if constexpr (LPS >= 32)
-        v += __shfl_xor(v, 16);
+    if constexpr (LPS == 32)
+        v = sum_xor(v, 16);
     return v;
 }
 

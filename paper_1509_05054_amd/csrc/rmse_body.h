@@ -66,7 +66,7 @@ __device__ inline float lanes_sum(float v, int lpu)
     if (lpu >= 16)
         v += dpp_mov_f<0x140>(v);  // row_mirror
     for (int off = 16; off < lpu; off <<= 1)
-        v += __shfl_xor(v, off);
+        v = sum_xor(v, off);
     return v;
 }
 

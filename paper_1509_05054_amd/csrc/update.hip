@@ -94,7 +94,7 @@ __device__ inline void pass1_body(const UpdateArgs &a, int a0, int a1, int blk, 
         for (int off = lpu; off < 64; off <<= 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                acc[r] += __shfl_xor(acc[r], off);
+                acc[r] = off >= 16 ? sum_xor(acc[r], off) : acc[r] + __shfl_xor(acc[r], off);
         }
         red[wave][lane] = acc;
         __syncthreads();
