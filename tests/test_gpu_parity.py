@@ -523,15 +523,16 @@ def test_omp_two_waves_per_signal_bitwise(s, m):
     np.testing.assert_array_equal(v2, v3)
 
 
-@pytest.mark.parametrize("lps,npl", [(16, 16), (32, 8), (64, 4), (64, 16), (32, 16), (128, 8),
-                                     (128, 4)])
-def test_omp_launch_shapes_agree(lps, npl):
+@pytest.mark.parametrize("lps,npl,s", [(16, 16, 6), (32, 8, 6), (64, 4, 6), (64, 16, 6),
+                                       (32, 16, 6), (128, 8, 6), (128, 4, 6), (32, 16, 12),
+                                       (32, 8, 12), (64, 4, 12), (16, 16, 12)])
+def test_omp_launch_shapes_agree(lps, npl, s):
     """Every launch shape of the OMP kernel computes the same supports and
     coefficients (only the summation order of ||y|| differs)."""
-    note(f"omp launch shape lps={lps} npl={npl}")
+    note(f"omp launch shape lps={lps} npl={npl} s={s}")
     Y, D = _patch_problem(64, 256, 3001, seed=77)
-    i0, v0, _ = gpu_omp(D, Y, 6)
-    i1, v1, _ = gpu_omp(D, Y, 6, omp_lanes_per_signal=lps, omp_atoms_per_lane=npl)
+    i0, v0, _ = gpu_omp(D, Y, s)
+    i1, v1, _ = gpu_omp(D, Y, s, omp_lanes_per_signal=lps, omp_atoms_per_lane=npl)
     assert np.mean(np.all(i0 == i1, axis=1)) >= 0.999
     same = np.all(i0 == i1, axis=1)
     np.testing.assert_array_equal(v0[same], v1[same])
