@@ -221,6 +221,34 @@ __device__ inline void load_row(vec_t<NPL> &v, const float *row, int first, int 
     }
 }
 
+// The same loads from a G row given by its byte offset from G (G is at most
+// 1024 x 1024 floats, so every byte offset fits in 32 bits): the address is
+// G's base, which is the same in every lane, plus a 32-bit lane offset, and
+// needs no 64-bit arithmetic per lane.
+template <int NPL>
+__device__ inline void load_grow(vec_t<NPL> &v, const float *G, unsigned row_bytes, int first,
+                                 int ldn, bool on)
+{
+    const char *base = reinterpret_cast<const char *>(G);
+#pragma unroll
+    for (int c4 = 0; c4 < NPL / 4; ++c4) {
+        const int at = first + 4 * c4;
+        f32x4 x = {0.f, 0.f, 0.f, 0.f};
+        if (on && at < ldn)
+            x = *reinterpret_cast<const f32x4 *>(base + (row_bytes + 4u * (unsigned)at));
+        v[4 * c4 + 0] = x[0];
+        v[4 * c4 + 1] = x[1];
+        v[4 * c4 + 2] = x[2];
+        v[4 * c4 + 3] = x[3];
+    }
+}
+
+__device__ inline float load_g(const float *G, unsigned row_bytes, int col)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(G) +
+                                            (row_bytes + 4u * (unsigned)col));
+}
+
 // The GPW = 64 / LPS signals [wave_sig0, wave_sig0 + GPW) of one wave
 // (signals at or beyond m_eff are skipped); waves never wait for each other.
 //
@@ -328,14 +356,14 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
         }
         bool ok = active && best > thr && bidx < n;
         const int j = ok ? bidx : 0;
-        const float *Gj = a.G + (size_t)j * ldn;
+        const unsigned gj_bytes = 4u * (unsigned)(j * ldn);  // row j of G
 
         // 2. loads for this step: the G row (NaN at j), G_jj, A0_j, and G[j][I_l]
         vec_t<NPL> g;
-        load_row<NPL>(g, Gj, a_first, ldn, ok);
+        load_grow<NPL>(g, a.G, gj_bytes, a_first, ldn, ok);
         const float gjj = ok ? a.Gdiag[j] : 1.f;
         const float a0j = ok ? a.A0[(size_t)i * ldn + j] : 0.f;
-        float acc = (ok && l < k) ? Gj[selj] : 0.f;
+        float acc = (ok && l < k) ? load_g(a.G, gj_bytes, selj) : 0.f;
 
         // forward substitution L w = G[I, j]: round t finalises w_t in lane t
         float w[US];
@@ -372,7 +400,7 @@ __device__ __forceinline__ void omp_signals(const OmpArgs &a, int wave_sig0, int
                 for (int r = 0; r < SMAX; ++r)
                     if (r <= l)
                         sL[wave][grp][l * SMAX + r] = Lrow[r];
-                sB[wave][grp][l] = Gj[selj];
+                sB[wave][grp][l] = load_g(a.G, gj_bytes, selj);
             }
             wave_lds_sync();
             if (need64 && l == 0) {
